@@ -1,0 +1,178 @@
+"""Benchmark of the distributed FFT hot path on one MI355X.
+
+A step is one forward plus one backward transform (every partial transform
+and every fused redistribution of both chains) of the workload's array, with
+the input already resident in HBM.  Default workload: 512^3 complex64, pencil
+decomposition on an 8x8 virtual-rank grid (two redistributions per direction,
+each fused into the next partial transform's kernel).
+
+Prints ONE JSON line.  `value` is milliseconds per forward+backward (lower is
+better); `pct_hbm_peak` is the algorithmic traffic of a step (each partial
+transform reads and writes the array once) over the step time, as a fraction
+of the MI355X's 8 TB/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # bytes/s, MI355X published peak
+
+WORKLOADS = {
+    # name: (shape, grid, kind, precision, chain)
+    "pencil512": ((512, 512, 512), (8, 8), "c2c", "f32", None),
+    "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
+    "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
+    "r2c512": ((512, 512, 512), (8, 8), "r2c", "f32", None),
+    "c2c4d64": ((64, 64, 64, 64), (2, 2, 4), "c2c", "f32", None),
+}
+
+KIND_NAMES = {"c2c": "c2c_stage", "copy": "redistribute_copy", "r2c": "r2c_stage", "c2r": "c2r_stage"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="pencil512", choices=sorted(WORKLOADS))
+    ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
+    return ap.parse_args()
+
+
+def kernel_name(rec):
+    base = KIND_NAMES.get(rec["kind"], rec["kind"])
+    mode = "contig" if rec["contig"] else "strided"
+    return "%s_%s_n%d" % (base, mode, rec["length"])
+
+
+def cpu_baseline(shape, grid, kind, chain, u_np):
+    """The FP64 oracle on the host cores: one forward + backward of the same
+    workload (the full array: ~10-40 s of CPU work)."""
+    import numpy as np
+    import oracle
+
+    ch = oracle.Chain.paper(shape, grid, kind=kind, steps=chain)
+    x = u_np.astype(np.complex128 if kind == "c2c" else np.float64)
+    t0 = time.perf_counter()
+    y = oracle.forward(ch, x)
+    oracle.backward(ch, y)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(dt * 1e3, 1), "unit": "ms per forward+backward", "cores": cores, "kind": "oracle",
+            "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the virtual ranks of the decomposition share one device; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1804_09536_amd import inputs
+    from paper_1804_09536_amd.plan import Plan
+
+    shape, grid, kind, prec, chain = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev).bind()
+    n_in = plan.buffer_numel(0, real=(kind == "r2c"))
+    if kind == "c2c":
+        u_np = inputs.uniform_complex(n_in, [4], np.complex64 if prec == "f32" else np.complex128)
+    else:
+        u_np = inputs.gaussian_real(n_in, [2], np.float32 if prec == "f32" else np.float64)
+    x = torch.from_numpy(u_np).to(dev)
+    y = plan.empty(plan.num_layouts - 1)
+    z = plan.empty(0, real=(kind == "r2c"))
+    work = plan.workspace()
+
+    def step():
+        plan.forward(x, out=y, work=work)
+        plan.backward(y, out=z, work=work)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile_read()
+    if not args.no_profile:
+        plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_profiling(False)
+    recs = plan.profile_read() if not args.no_profile else []
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # algorithmic bytes of one step: every launch of forward and backward
+    step_bytes = 0.0
+    per_kernel = {}
+    for r in recs:
+        k = kernel_name(r)
+        d = per_kernel.setdefault(k, {"ms": 0.0, "n": 0, "bytes": 0.0})
+        d["ms"] += r["ms"]
+        d["n"] += 1
+        d["bytes"] += r["bytes"]
+        step_bytes += r["bytes"]
+    step_bytes /= max(1, args.steps)
+    roofline = None
+    if per_kernel:
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
+        d = per_kernel[dom]
+        avg_ms = d["ms"] / d["n"]
+        per_launch = d["bytes"] / d["n"]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": 8000.0,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                    "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": per_launch}
+    # round-trip sanity on the last step
+    zz = z.float() if kind == "c2c" else z
+    rt = float(torch.linalg.vector_norm((zz - x.to(zz.dtype)).flatten()) / torch.linalg.vector_norm(x.flatten()))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(shape, grid, kind, chain, u_np)
+
+    out = {
+        "metric": "fwd+bwd 3D FFT ms & %HBM peak, 512^3 c2c FP32; batched/adjoint vs plain path",
+        "value": round(ms_per_step, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": "%s %s %s on a %s virtual-rank grid, forward+backward, %s path"
+                               % ("x".join(map(str, shape)), kind, "complex64" if prec == "f32" else "complex128",
+                                  "x".join(map(str, grid)), args.path),
+                   "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path},
+        "step_bytes": step_bytes,
+        "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
+        "roundtrip_rel_l2": rt,
+        "per_kernel_avg_ms": {k: round(v["ms"] / v["n"], 4) for k, v in per_kernel.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

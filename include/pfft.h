@@ -1,0 +1,218 @@
+/*
+ * pfft.h -- C ABI of libpfft: the transpose-based parallel multidimensional
+ * FFT of Dalcin, Mortensen & Keyes ("Fast parallel multidimensional FFT using
+ * advanced MPI", arXiv:1804.09536) for one AMD Instinct MI355X (gfx950).
+ *
+ * Model.  A d-dimensional array (C row-major, Sec. 3) is decomposed over a
+ * Cartesian grid of P "virtual ranks" (Sec. 3.3; ranks are numbered row-major
+ * over their grid coordinates).  Each axis is either whole on every rank or
+ * split over one grid direction with the balanced block-contiguous rule of
+ * Eq. decompose (Sec. 3.1).  One *layout* (alignment) of the array is the
+ * concatenation, in rank order, of every rank's local block, each block a
+ * C-order array.  All ranks' blocks of one layout live in ONE device buffer.
+ *
+ * A plan walks a chain of layouts.  With the paper's rule (Secs. 3.2.1, 3.4,
+ * 3.5) grid direction i starts on axis i and redistribution t = 1..g moves
+ * direction g-t from axis g-t to axis g-t+1 (slab: 1 -> 0; pencil: 2 -> 1 then
+ * 1 -> 0; 4-D on a 3-D grid: 3 -> 2 -> 1 -> 0).  The forward transform applies
+ * the partial transforms last axis first (Eq. fftn_forward), each on the first
+ * layout of the chain where its axis is whole; the backward runs the mirror
+ * chain (Eq. fftn_backward).  Every redistribution is a pure permutation
+ * (Eq. gt) and is fused into the load of the next partial transform's kernel,
+ * so the chain costs one HBM read and one HBM write per partial transform.
+ *
+ * Layout indices in this API count along the chain: 0 is the input layout
+ * (aligned in the last axis for the paper's rule), pfft_num_layouts()-1 the
+ * forward output layout.
+ *
+ * Conventions.  Forward sign -1, backward +1 (Eqs. 1-2).  Normalisation
+ * PFFT_NORM_FORWARD is the paper's (1/N_m on each forward partial transform,
+ * Eq. multifft), PFFT_NORM_BACKWARD puts it on the backward, PFFT_NORM_NONE
+ * nowhere.  Complex data is interleaved (re, im): complex64 for PFFT_F32,
+ * complex128 for PFFT_F64.  A PFFT_R2C plan takes a real array (float or
+ * double) and produces the half spectrum N_{d-1}/2+1 along the last axis
+ * (footnote of Sec. 2); its backward is the matching complex-to-real
+ * transform, which ignores the imaginary parts of bins 0 and N/2.
+ *
+ * Memory.  The library never allocates device memory.  The caller allocates
+ * the device state (pfft_device_state_bytes), binds it once
+ * (pfft_bind_device_state), and passes input, output and workspace buffers
+ * to every call.  All transform calls are asynchronous on the given stream,
+ * out-of-place, never write their input, and make no host synchronisation;
+ * they may be captured into a HIP graph.  Pointers are device pointers unless
+ * stated otherwise.  A plan is immutable after binding; calls on different
+ * streams may share a plan if each call has its own output and workspace.
+ *
+ * Errors.  Every function returns an int status: PFFT_OK (0) or a negative
+ * code below.  No function aborts or throws.  pfft_strerror() names a code.
+ */
+#ifndef PFFT_H
+#define PFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfft_plan_s *pfft_plan;
+
+enum { PFFT_C2C = 0, PFFT_R2C = 1 };
+enum { PFFT_F32 = 0, PFFT_F64 = 1 };
+enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
+
+/* plan flags */
+#define PFFT_PATH_FUSED 0u        /* redistribution fused into the next transform's load (default) */
+#define PFFT_PATH_UNFUSED 1u      /* standalone redistribution kernel, then transform in place of the new layout */
+#define PFFT_PATH_PACK_REALIGN 2u /* traditional method: local transpose, contiguous exchange, realign (Sec. 3.2.1) */
+#define PFFT_PATH_MASK 3u
+#define PFFT_LAYOUTS_ONLY 4u      /* plan layouts and redistributions only: no transform kernels are
+                                     set up (any lengths), pfft_forward & co. return PFFT_EUNSUPPORTED */
+
+/* status codes */
+#define PFFT_OK 0
+#define PFFT_EINVAL (-1)       /* null pointer, bad enum or index */
+#define PFFT_ESHAPE (-2)       /* bad global shape */
+#define PFFT_EGRID (-3)        /* bad virtual process grid or chain */
+#define PFFT_EDTYPE (-4)       /* bad precision / kind */
+#define PFFT_EUNSUPPORTED (-5) /* a transform length with no kernel */
+#define PFFT_EWORKSPACE (-6)   /* device state not bound, or buffer too small */
+#define PFFT_EHIP (-7)         /* a HIP runtime call failed */
+#define PFFT_EINTERNAL (-8)
+
+#define PFFT_MAX_DIMS 8
+
+/*
+ * Create a plan (host memory only).
+ *   ndim, global_shape: the global array, 1 <= ndim <= 8, every extent >= 1.
+ *     For PFFT_R2C, global_shape is the real array's shape.
+ *   grid_ndim, grid_dims: the virtual process grid, 1 <= grid_ndim < ndim,
+ *     every extent >= 1; P = product of grid_dims virtual ranks.  A direction
+ *     may be larger than the axis it splits (those ranks get empty blocks).
+ *   precision: PFFT_F32 or PFFT_F64.  kind: PFFT_C2C or PFFT_R2C.
+ *   norm: PFFT_NORM_*.
+ *   chain: NULL for the paper's rule, else 2*nsteps ints {dir, new_axis}: step
+ *     s moves grid direction dir onto axis new_axis (which must be whole
+ *     before the step).  Initially direction i splits axis i.
+ *   nsteps: number of chain steps (ignored when chain is NULL).
+ *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
+ *     or-ed with PFFT_LAYOUTS_ONLY.
+ * The chain must leave every axis transformed (each axis whole in some
+ * layout).  For PFFT_R2C the last axis must be whole in layout 0.
+ * Returns PFFT_OK and *out, or an error (then *out is NULL).
+ */
+int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim,
+                     const int *grid_dims, int precision, int kind, int norm, const int *chain,
+                     int nsteps, unsigned flags);
+
+/* Destroy a plan (host memory).  The caller frees the device state. */
+int pfft_plan_destroy(pfft_plan plan);
+
+/* Number of layouts in the chain (g+1 for the paper's rule). */
+int pfft_num_layouts(pfft_plan plan, int *n);
+
+/*
+ * Rank `rank`'s block in chain layout `layout` (the role of the appendix
+ * programs' local-size helper).  shape/start receive ndim extents / global
+ * starts; *offset the block's first element in the layout's buffer.  For
+ * PFFT_R2C plans layout 0 is described in the real shape when `real` is
+ * nonzero, else every layout in the half-spectrum shape.
+ */
+int pfft_local_block(pfft_plan plan, int layout, int real, int rank, int64_t *shape, int64_t *start,
+                     int64_t *offset);
+
+/* Bytes of a layout's buffer (real = as above). */
+int pfft_buffer_bytes(pfft_plan plan, int layout, int real, size_t *bytes);
+
+/* Bytes of device state (tile and index tables, twiddles) the plan needs. */
+int pfft_device_state_bytes(pfft_plan plan, size_t *bytes);
+
+/*
+ * Upload the plan's tables into caller-allocated device memory `dev`
+ * (>= pfft_device_state_bytes, 256-byte aligned) on `stream`, then wait for
+ * the copy.  Must precede every call below.  The memory must outlive the
+ * plan's use; binding again (e.g. to another buffer) is allowed.
+ */
+int pfft_bind_device_state(pfft_plan plan, void *dev, hipStream_t stream);
+
+/* Workspace bytes needed by pfft_forward/backward/adjoint_* (256-aligned). */
+int pfft_workspace_bytes(pfft_plan plan, size_t *bytes);
+
+/*
+ * Global redistribution (Eq. gt) between chain layouts layout_from and
+ * layout_to = layout_from +/- 1 (they differ by exactly one exchange): for
+ * every global index g, out[to(g)] = in[from(g)], bit-exact.  Elements are
+ * the plan's complex type (for R2C plans: the half-spectrum layouts).
+ */
+int pfft_redistribute(pfft_plan plan, int layout_from, int layout_to, const void *in, void *out,
+                      hipStream_t stream);
+
+/*
+ * Forward transform: `in` in layout 0 (real for R2C), `out` in the last
+ * layout (half spectrum for R2C).  `work`: pfft_workspace_bytes bytes.
+ */
+int pfft_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
+
+/* Backward transform: `in` in the last layout, `out` in layout 0. */
+int pfft_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
+
+/*
+ * Adjoint of pfft_forward under the real inner product Re<a,b> (the gradient
+ * map for automatic differentiation): reversed chain, inverse
+ * redistributions, sign +1 and the forward's per-axis factors; for R2C the
+ * result is Re(F^H S^T z), i.e. a complex-to-real with interior bins halved.
+ * `in` in the last layout, `out` in layout 0.
+ */
+int pfft_adjoint_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
+
+/* Adjoint of pfft_backward: forward chain, sign -1, the backward's factors;
+ * for R2C an r2c with interior bins doubled. */
+int pfft_adjoint_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
+
+/*
+ * Host-side self-check of a plan (no device needed): emulates the address
+ * arithmetic of every kernel launch the plan can make and verifies that each
+ * access stays inside its rank block and buffer and that every destination
+ * element is written exactly once.  Returns PFFT_OK or PFFT_EINTERNAL (see
+ * pfft_last_error).  Cost is proportional to the array size.
+ */
+int pfft_validate_plan(pfft_plan plan);
+
+/*
+ * Per-launch timing.  While enabled, every kernel launch of later calls on
+ * this plan is bracketed by two HIP events recorded on the call's stream (no
+ * host synchronisation).  pfft_profile_read waits for the logged launches,
+ * fills up to max_entries records (oldest first), sets *n to the number
+ * logged, and clears the log.  kind: 0 complex transform, 1 redistribution
+ * copy, 2 real-to-complex, 3 complex-to-real; direction: 0 forward, 1 backward,
+ * 2 adjoint of forward, 3 adjoint of backward, 4 pfft_redistribute; bytes: the
+ * launch's algorithmic traffic (source read once + destination written once).
+ * Not for use while a call on the plan is being captured into a graph.
+ */
+typedef struct {
+    int kind;
+    int axis;
+    int contig;
+    int length;
+    int direction;
+    float ms;
+    double bytes;
+} pfft_profile_entry;
+
+int pfft_set_profiling(pfft_plan plan, int enable);
+int pfft_profile_read(pfft_plan plan, int max_entries, pfft_profile_entry *entries, int *n);
+
+/* Human-readable name of a status code (static string). */
+const char *pfft_strerror(int status);
+
+/* Last error detail for this thread (static buffer), e.g. the HIP message. */
+const char *pfft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFFT_H */

@@ -1,0 +1,32 @@
+// dispatch.cpp -- routes a stage to its kernel family.
+#include "pfft_kernels.hpp"
+
+namespace pfft {
+
+int kernel_config(int kind, int prec, int N, int contig, KernelConfig *cfg)
+{
+    switch (kind) {
+    case KIND_C2C: return prec == 0 ? c2c_config_f32(N, contig, cfg) : c2c_config_f64(N, contig, cfg);
+    case KIND_COPY: return copy_config(N, cfg);
+    case KIND_R2C:
+    case KIND_C2R:
+        if (!contig) return -1;
+        return real_config(prec, N, kind, cfg);
+    default: return -1;
+    }
+}
+
+int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelConfig &cfg, size_t esize,
+                 const StageArgs &a, hipStream_t s)
+{
+    switch (kind) {
+    case KIND_C2C:
+        return (int)(prec == 0 ? c2c_launch_f32(N, contig, sign, cfg, a, s) : c2c_launch_f64(N, contig, sign, cfg, a, s));
+    case KIND_COPY: return (int)copy_launch(esize, cfg, a, s);
+    case KIND_R2C:
+    case KIND_C2R: return (int)real_launch(prec, N, kind, cfg, a, s);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+}  // namespace pfft

@@ -1,0 +1,307 @@
+// fft_device.hpp -- device building blocks of libpfft's stage kernels for
+// gfx950: complex arithmetic, radix-2^k butterflies, the LDS-staged Stockham
+// passes, and the index arithmetic that reads a line from whichever virtual
+// ranks' blocks hold it (the subarray gather of the exchange, Sec. 3.2.2,
+// done by address computation instead of a separate copy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pfft_internal.hpp"
+
+namespace pfft {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+    using type = float2;
+    using quad = float4;
+};
+template <>
+struct V2<double> {
+    using type = double2;
+    using quad = double4;
+};
+
+template <typename T2>
+__device__ __forceinline__ T2 c_add(T2 a, T2 b)
+{
+    T2 r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename T2>
+__device__ __forceinline__ T2 c_sub(T2 a, T2 b)
+{
+    T2 r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename T2>
+__device__ __forceinline__ T2 c_mul(T2 a, T2 b)
+{
+    T2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename T2, typename T>
+__device__ __forceinline__ T2 c_scale(T2 a, T s)
+{
+    T2 r;
+    r.x = a.x * s;
+    r.y = a.y * s;
+    return r;
+}
+template <typename T2>
+__device__ __forceinline__ T2 c_zero()
+{
+    T2 r;
+    r.x = 0;
+    r.y = 0;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Radix-R DFT in registers, R = 1, 2, 4, 8, 16:  a_s <- sum_r a_r w^{SIGN r s},
+// w = e^{2 pi i / R}.  Built by even/odd splitting; multiplications by the
+// exact roots 1, -1, +-i are done by sign changes and swaps.
+
+// cos(2 pi k / 16) and sin(2 pi k / 16), k = 0..7
+#define PFFT_C1 0.92387953251128675613
+#define PFFT_S1 0.38268343236508977173
+#define PFFT_H 0.70710678118654752440
+
+template <int R, int SIGN, int S, typename T2>
+__device__ __forceinline__ T2 root_mul(T2 x)
+{
+    using T = decltype(x.x);
+    constexpr int k = (16 / R) * S;  // exponent in units of 2 pi / 16, 0 <= k < 8
+    static_assert(k >= 0 && k < 8, "root index");
+    T2 r;
+    if constexpr (k == 0) {
+        return x;
+    } else if constexpr (k == 4) {  // w = SIGN * i
+        if constexpr (SIGN > 0) {
+            r.x = -x.y;
+            r.y = x.x;
+        } else {
+            r.x = x.y;
+            r.y = -x.x;
+        }
+        return r;
+    } else if constexpr (k == 2) {  // w = (1 + SIGN i) / sqrt 2
+        const T h = (T)PFFT_H;
+        if constexpr (SIGN > 0) {
+            r.x = (x.x - x.y) * h;
+            r.y = (x.y + x.x) * h;
+        } else {
+            r.x = (x.x + x.y) * h;
+            r.y = (x.y - x.x) * h;
+        }
+        return r;
+    } else if constexpr (k == 6) {  // w = (-1 + SIGN i) / sqrt 2
+        const T h = (T)PFFT_H;
+        if constexpr (SIGN > 0) {
+            r.x = (-x.x - x.y) * h;
+            r.y = (-x.y + x.x) * h;
+        } else {
+            r.x = (-x.x + x.y) * h;
+            r.y = (-x.y - x.x) * h;
+        }
+        return r;
+    } else {
+        // k = 1, 3, 5, 7
+        constexpr double cs[8] = {1.0, PFFT_C1, PFFT_H, PFFT_S1, 0.0, -PFFT_S1, -PFFT_H, -PFFT_C1};
+        constexpr double sn[8] = {0.0, PFFT_S1, PFFT_H, PFFT_C1, 1.0, PFFT_C1, PFFT_H, PFFT_S1};
+        T2 w;
+        w.x = (T)cs[k];
+        w.y = (T)(SIGN * sn[k]);
+        return c_mul(x, w);
+    }
+}
+
+template <int R, int SIGN, int S, typename T2>
+__device__ __forceinline__ void radix_combine(T2 *a, const T2 *e, const T2 *o)
+{
+    if constexpr (S < R / 2) {
+        T2 t = root_mul<R, SIGN, S>(o[S]);
+        a[S] = c_add(e[S], t);
+        a[S + R / 2] = c_sub(e[S], t);
+        radix_combine<R, SIGN, S + 1>(a, e, o);
+    }
+}
+
+template <int R, int SIGN, typename T2>
+__device__ __forceinline__ void dft_regs(T2 *a)
+{
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        T2 t = a[0];
+        a[0] = c_add(t, a[1]);
+        a[1] = c_sub(t, a[1]);
+    } else {
+        constexpr int H = R / 2;
+        T2 e[H], o[H];
+#pragma unroll
+        for (int i = 0; i < H; i++) {
+            e[i] = a[2 * i];
+            o[i] = a[2 * i + 1];
+        }
+        dft_regs<H, SIGN>(e);
+        dft_regs<H, SIGN>(o);
+        radix_combine<R, SIGN, 0>(a, e, o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Radix plan of an N-point line (N a power of two, 2 <= N <= 4096).  Each
+// thread of a line owns P points; every pass has radix R dividing P.
+
+__host__ __device__ constexpr int fft_points(int N) { return N <= 16 ? N : (N <= 512 ? 8 : 16); }
+
+__host__ __device__ constexpr int fft_npasses(int N)
+{
+    int P = fft_points(N), n = 0, rem = N;
+    while (rem > 1) {
+        rem = rem >= P ? rem / P : 1;
+        n++;
+    }
+    return n;
+}
+
+__host__ __device__ constexpr int fft_radix(int N, int pass)
+{
+    int P = fft_points(N), rem = N;
+    for (int i = 0; i < pass; i++) rem = rem >= P ? rem / P : 1;
+    return rem >= P ? P : rem;
+}
+
+__host__ __device__ constexpr int fft_span(int N, int pass)  // L = product of radices before `pass`
+{
+    int L = 1;
+    for (int i = 0; i < pass; i++) L *= fft_radix(N, i);
+    return L;
+}
+
+// Butterflies of one pass on the P registers of one line slot.  Register m
+// holds position jt + m*TPL of the line on entry (for every pass) and, after
+// the butterflies, output (b, s) of butterfly b sits in register b + s*(P/R).
+template <typename T2, int N, int P, int R, int L, int SIGN>
+__device__ __forceinline__ void pass_butterflies(T2 (&v)[P], int jt, const T2 *__restrict__ tw)
+{
+    constexpr int TPL = N / P;
+    constexpr int NB = P / R;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        T2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) x[r] = v[b + r * NB];
+        if constexpr (L > 1) {
+            const int q = jt + b * TPL;
+            const int k = q & (L - 1);
+#pragma unroll
+            for (int r = 1; r < R; r++) {
+                T2 w = tw[r * k * (N / (L * R))];
+                if constexpr (SIGN > 0) w.y = -w.y;
+                x[r] = c_mul(x[r], w);
+            }
+        }
+        dft_regs<R, SIGN>(x);
+#pragma unroll
+        for (int s = 0; s < R; s++) v[b + s * NB] = x[s];
+    }
+}
+
+// Position in the line of output (b, s) of a pass.
+template <int N, int P, int R, int L>
+__device__ __forceinline__ int pass_out_index(int jt, int b, int s)
+{
+    constexpr int TPL = N / P;
+    const int q = jt + b * TPL;
+    return (q / L) * (L * R) + s * L + (q & (L - 1));
+}
+
+// LDS addressing of a tile of W lines of N points.
+//  strided tiles: point-major, lines contiguous, rows padded by 16 bytes;
+//  contiguous tiles: line-major, one pad element after every 8 points.
+template <typename T2, int N, int W, bool CONTIG>
+struct LdsTile {
+    static constexpr int PADW = 16 / (int)sizeof(T2) > 0 ? 16 / (int)sizeof(T2) : 1;
+    static constexpr int ROW = W + PADW;
+    static constexpr int LINE = N + N / 8;
+    static constexpr int SIZE = CONTIG ? W * LINE : N * ROW;
+    __device__ static __forceinline__ int idx(int w, int j)
+    {
+        if constexpr (CONTIG)
+            return w * LINE + j + (j >> 3);
+        else
+            return j * ROW + w;
+    }
+};
+
+// Run all passes of an N-point transform on the register sets of NL line
+// slots (lines w_l of the tile), staging through LDS between passes.  On
+// entry register m of slot l holds point jt + m*TPL of line w_l; on exit the
+// transform's output point jt + m*TPL.
+template <typename T2, int N, int W, bool CONTIG, int SIGN, int NL, int PASS>
+__device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int (&wl)[NL], int jt, T2 *lds,
+                                           const T2 *__restrict__ tw)
+{
+    constexpr int P = fft_points(N);
+    constexpr int NP = fft_npasses(N);
+    constexpr int R = fft_radix(N, PASS);
+    constexpr int L = fft_span(N, PASS);
+    constexpr int TPL = N / P;
+    using LT = LdsTile<T2, N, W, CONTIG>;
+#pragma unroll
+    for (int l = 0; l < NL; l++) pass_butterflies<T2, N, P, R, L, SIGN>(v[l], jt, tw);
+    if constexpr (PASS + 1 < NP) {
+        if constexpr (PASS > 0) __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+#pragma unroll
+            for (int b = 0; b < P / R; b++)
+#pragma unroll
+                for (int s = 0; s < R; s++)
+                    lds[LT::idx(wl[l], pass_out_index<N, P, R, L>(jt, b, s))] = v[l][b + s * (P / R)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l], jt + m * TPL)];
+        fft_passes<T2, N, W, CONTIG, SIGN, NL, PASS + 1>(v, wl, jt, lds, tw);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Addressing of one side of a stage for the P positions a thread owns.
+// Offsets are 32-bit (the plan guarantees every buffer has < 2^31 elements).
+template <int P>
+struct SideAddr {
+    int off[P];     // element offset of position m in line 0 of the tile
+    int stride[P];  // distance between consecutive lines of the tile
+
+    __device__ __forceinline__ void init(const Side &sd, const Tile &t, int s, int jt, int TPL, int N, bool contig)
+    {
+        const int rank = t.rank[s];
+        const long O = t.O[s], E = t.E[s], I = t.I[s];
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            int j = jt + m * TPL;
+            if (j >= N) j = N - 1;  // callers mask positions past the end
+            const int2 pc = sd.pos[j];
+            const long na = sd.na[pc.x];
+            const long base = sd.rank_off[rank + pc.x * sd.R];
+            off[m] = (int)(base + (O * na + pc.y) * E + I);
+            stride[m] = contig ? (int)(na * E) : 1;
+        }
+    }
+};
+
+}  // namespace pfft

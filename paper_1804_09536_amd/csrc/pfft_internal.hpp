@@ -1,0 +1,69 @@
+// pfft_internal.hpp -- structures shared by the host plan engine and the HIP
+// kernels of libpfft.  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+namespace pfft {
+
+constexpr int kMaxDims = 8;
+
+// One line tile of a stage: up to W lines that share, on both the source
+// side (0) and the destination side (1), the virtual rank coordinates of every
+// grid direction except the one splitting the transform axis, the local
+// "outer" index O (C-order index over the axes before the transform axis) and
+// the inner extent E (product of local extents after it).  Lines w = 0..count-1
+// differ only by +w in O (contiguous mode: transform axis is the last axis)
+// or by +w in the inner index I (strided mode).
+//
+// The element at position j of line w on side s lives at
+//   rank_off[rank + c(j)*R] + ((O + w*dO) * na[c(j)] + loc(j)) * E + I + w*dI
+// where (c(j), loc(j)) = pos[j] names the block along the transform axis and
+// the local index there, na[c] is that block's local extent of the axis and R
+// the rank stride of the grid direction splitting it (0 if whole).
+struct Tile {
+    int32_t rank[2];
+    int32_t count;
+    int32_t pad_;
+    int64_t O[2];
+    int64_t E[2];
+    int64_t I[2];
+};
+static_assert(sizeof(Tile) == 64, "Tile must be 64 bytes");
+
+struct Side {
+    const int64_t *rank_off;  // element offset of each rank's block
+    const int2 *pos;          // per position along the axis: (block, local index)
+    const int32_t *na;        // per block along the axis: local extent
+    int32_t R;                // rank stride of the direction splitting the axis
+    int32_t pad_;
+};
+
+// Kind of a stage kernel.
+enum StageKind : int32_t {
+    KIND_C2C = 0,   // complex line transform
+    KIND_COPY = 1,  // pure permutation of lines (redistribution)
+    KIND_R2C = 2,   // real line of N -> N/2+1 bins
+    KIND_C2R = 3,   // N/2+1 bins -> real line of N
+};
+
+// Flags of a stage launch.
+enum StageFlags : int32_t {
+    SF_HALVE_INTERIOR = 1,   // C2R: halve bins 0<k<N-k first (adjoint of R2C)
+    SF_DOUBLE_INTERIOR = 2,  // R2C: double bins 0<k<N-k after (adjoint of C2R)
+};
+
+struct StageArgs {
+    const void *src;
+    void *dst;
+    Side side[2];
+    const Tile *tiles;
+    const void *twiddle;  // N entries e^{-2 pi i m / N} (R2C/C2R: N/2-point table + N-point post table)
+    const void *twiddle2;
+    int64_t ntiles;
+    double scale;
+    int32_t N;      // positions per line on the complex side (C2C/COPY); real length for R2C/C2R
+    int32_t flags;
+};
+
+}  // namespace pfft

@@ -1,0 +1,40 @@
+// pfft_kernels.hpp -- host-side interface between the plan engine and the
+// HIP kernels of libpfft.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "pfft_internal.hpp"
+
+namespace pfft {
+
+// Launch shape of a stage kernel: at most W lines per tile, `threads` per
+// workgroup; `id` selects a variant in the dispatch tables.
+struct KernelConfig {
+    int W = 0;
+    int threads = 0;
+    int id = 0;
+};
+
+// Fills cfg for a stage kernel (kind: StageKind; prec: 0 = f32, 1 = f64;
+// N: line length; contig: transform axis is the last axis).  Returns 0, or
+// -1 if there is no kernel for this combination.
+int kernel_config(int kind, int prec, int N, int contig, KernelConfig *cfg);
+
+// Enqueue one stage on `stream`.  esize: element bytes for KIND_COPY.
+// Returns a hipError_t value (0 on success).
+int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelConfig &cfg, size_t esize,
+                 const StageArgs &args, hipStream_t stream);
+
+// Per-precision tables (defined in the c2c kernel files).
+int c2c_config_f32(int N, int contig, KernelConfig *cfg);
+int c2c_config_f64(int N, int contig, KernelConfig *cfg);
+hipError_t c2c_launch_f32(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+hipError_t c2c_launch_f64(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+int copy_config(int N, KernelConfig *cfg);
+hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+int real_config(int prec, int N, int kind, KernelConfig *cfg);
+hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+
+}  // namespace pfft

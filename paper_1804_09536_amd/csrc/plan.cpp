@@ -1,0 +1,994 @@
+// plan.cpp -- host plan engine and C ABI of libpfft.
+//
+// Implements the decomposition (Sec. 3.1, Eq. decompose), the virtual
+// Cartesian grid with row-major rank numbering (Sec. 3.3), the chain of
+// alignments of the slab / pencil / higher-dimensional methods (Secs. 3.2.1,
+// 3.4, 3.5), the order of partial transforms (Eq. fftn_forward and
+// Eq. fftn_backward) and the setup-phase construction of the index tables
+// that the kernels use to move subarrays (the role the subarray datatypes of
+// Alg. SubArray play for Alg. Exchange, built once and reused, Sec. 3.2.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pfft.h"
+#include "pfft_internal.hpp"
+#include "pfft_kernels.hpp"
+
+namespace pfft {
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// Eq. decompose: part p of N elements split in M parts gets n = q + [r > p]
+// elements starting at s = q*p + min(r, p), with q = N div M, r = N mod M.
+static void decompose(int64_t N, int64_t M, int64_t p, int64_t *n, int64_t *s)
+{
+    int64_t q = N / M, r = N % M;
+    *n = q + (r > p ? 1 : 0);
+    *s = q * p + std::min(r, p);
+}
+
+// One alignment of the array over a (possibly extended) virtual grid.
+struct Layout {
+    int ndim = 0, ngrid = 0;
+    int64_t shape[kMaxDims] = {};
+    int64_t grid[kMaxDims] = {};
+    int axis_dir[kMaxDims] = {};
+    int64_t P = 1;
+    int64_t rstride[kMaxDims] = {};  // rank distance between neighbours along a direction
+    std::vector<int64_t> rank_off;   // P+1 prefix sums of block sizes
+    std::vector<int32_t> own[kMaxDims], loc[kMaxDims];
+    std::vector<int64_t> dir_n[kMaxDims];  // per direction d and coordinate c: local extent of the axis d splits
+
+    void init(int nd, const int64_t *shp, int ng, const int64_t *grd, const int *dirs)
+    {
+        ndim = nd;
+        ngrid = ng;
+        for (int m = 0; m < nd; m++) {
+            shape[m] = shp[m];
+            axis_dir[m] = dirs[m];
+        }
+        P = 1;
+        for (int i = 0; i < ng; i++) {
+            grid[i] = grd[i];
+            P *= grd[i];
+        }
+        for (int i = ng - 1, st = 1; i >= 0; i--) {
+            rstride[i] = st;
+            st *= (int)grd[i];
+        }
+        for (int m = 0; m < nd; m++) {
+            own[m].assign(shape[m], 0);
+            loc[m].assign(shape[m], 0);
+            int d = axis_dir[m];
+            if (d < 0) {
+                for (int64_t g = 0; g < shape[m]; g++) loc[m][g] = (int32_t)g;
+            } else {
+                dir_n[d].assign(grid[d], 0);
+                for (int64_t c = 0; c < grid[d]; c++) {
+                    int64_t n, s;
+                    decompose(shape[m], grid[d], c, &n, &s);
+                    dir_n[d][c] = n;
+                    for (int64_t g = s; g < s + n; g++) {
+                        own[m][g] = (int32_t)c;
+                        loc[m][g] = (int32_t)(g - s);
+                    }
+                }
+            }
+        }
+        rank_off.assign(P + 1, 0);
+        for (int64_t r = 0; r < P; r++) {
+            int64_t ls[kMaxDims], st[kMaxDims];
+            rank_off[r + 1] = rank_off[r] + block(r, ls, st);
+        }
+    }
+
+    void coords(int64_t r, int64_t *c) const
+    {
+        for (int i = ngrid - 1; i >= 0; i--) {
+            c[i] = r % grid[i];
+            r /= grid[i];
+        }
+    }
+
+    int64_t block(int64_t r, int64_t *ls, int64_t *st) const
+    {
+        int64_t c[kMaxDims];
+        coords(r, c);
+        int64_t cnt = 1;
+        for (int m = 0; m < ndim; m++) {
+            int d = axis_dir[m];
+            if (d < 0) {
+                ls[m] = shape[m];
+                st[m] = 0;
+            } else {
+                decompose(shape[m], grid[d], c[d], &ls[m], &st[m]);
+            }
+            cnt *= ls[m];
+        }
+        return cnt;
+    }
+
+    int64_t total() const { return rank_off[P]; }
+
+    // Local extent of axis m in a block whose coordinate along m's direction is c.
+    int64_t local_extent(int m, int64_t c) const
+    {
+        int d = axis_dir[m];
+        return d < 0 ? shape[m] : dir_n[d][c];
+    }
+};
+
+// One kernel launch of a direction's list.
+struct Launch {
+    int kind = KIND_C2C;
+    int axis = 0;
+    int N = 0;        // transform / line length
+    int contig = 1;   // transform axis is the last axis
+    int src = 0, dst = 0;  // layout ids
+    int sign = -1;
+    int scale_axis = -1;   // axis whose 1/N_m factor may apply (-1: none)
+    // device blob offsets
+    size_t off_tiles = 0;
+    int64_t ntiles = 0;
+    size_t off_pos[2] = {0, 0}, off_na[2] = {0, 0}, off_rank[2] = {0, 0};
+    int32_t R[2] = {0, 0};
+    size_t off_tw = 0, off_tw2 = 0;
+    KernelConfig cfg{};
+};
+
+}  // namespace pfft
+
+using namespace pfft;
+
+struct pfft_plan_s {
+    int ndim = 0;
+    int64_t shape[kMaxDims] = {};
+    int ngrid = 0;
+    int64_t grid[kMaxDims] = {};
+    int precision = PFFT_F32, kind = PFFT_C2C, norm = PFFT_NORM_FORWARD;
+    unsigned flags = 0;
+    int nlayouts = 0;                             // chain length
+    std::vector<std::array<int, kMaxDims>> dirs;  // per chain layout
+    std::vector<Layout> layouts;                  // 0..nlayouts-1: spectral; then extras
+    int real0 = -1;                               // id of the real input layout (R2C)
+    std::vector<std::pair<int, int>> sched;       // (chain layout, axis), forward order
+    std::vector<Launch> fwd, bwd;
+    std::vector<Launch> up, down;  // redistribution between chain neighbours
+    std::vector<uint8_t> blob;
+    std::map<std::pair<int, int>, std::array<size_t, 3>> side_cache;
+    std::map<int, std::pair<size_t, size_t>> tw_cache;
+    void *dev = nullptr;
+    size_t spec_bytes = 0;
+    size_t elem = 8;  // complex element bytes
+    // optional per-launch timing
+    bool profiling = false;
+    struct Prof {
+        int kind, axis, contig, N, direction;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<Prof> prof;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace pfft {
+
+static size_t blob_put(pfft_plan_s *p, const void *data, size_t bytes)
+{
+    size_t off = (p->blob.size() + 255) & ~(size_t)255;
+    p->blob.resize(off + std::max<size_t>(bytes, 1), 0);
+    if (bytes) memcpy(p->blob.data() + off, data, bytes);
+    return off;
+}
+
+// Side tables of layout `lid` for lines along `axis`: per position the block
+// index along the axis and the local index there; per block its local extent;
+// the per-rank offsets.
+static void side_tables(pfft_plan_s *p, int lid, int axis, size_t *off_pos, size_t *off_na, size_t *off_rank,
+                        int32_t *R)
+{
+    const Layout &L = p->layouts[lid];
+    auto key = std::make_pair(lid, axis);
+    auto it = p->side_cache.find(key);
+    int d = L.axis_dir[axis];
+    *R = d < 0 ? 0 : (int32_t)L.rstride[d];
+    if (it != p->side_cache.end()) {
+        *off_pos = it->second[0];
+        *off_na = it->second[1];
+        *off_rank = it->second[2];
+        return;
+    }
+    int64_t N = L.shape[axis];
+    std::vector<int32_t> pos(2 * N);
+    for (int64_t j = 0; j < N; j++) {
+        pos[2 * j] = L.own[axis][j];
+        pos[2 * j + 1] = L.loc[axis][j];
+    }
+    std::vector<int32_t> na;
+    if (d < 0)
+        na.push_back((int32_t)N);
+    else
+        for (int64_t c = 0; c < L.grid[d]; c++) na.push_back((int32_t)L.dir_n[d][c]);
+    *off_pos = blob_put(p, pos.data(), pos.size() * 4);
+    *off_na = blob_put(p, na.data(), na.size() * 4);
+    *off_rank = blob_put(p, L.rank_off.data(), L.rank_off.size() * 8);
+    p->side_cache[key] = {*off_pos, *off_na, *off_rank};
+}
+
+// Twiddle table e^{-2 pi i m / n}, m = 0..n-1, from FP64 libm cos/sin with the
+// angle reduced exactly in integers, rounded once to the plan precision.
+static size_t twiddle_table(pfft_plan_s *p, int n)
+{
+    auto it = p->tw_cache.find(n);
+    if (it != p->tw_cache.end()) return it->second.first;
+    size_t off;
+    if (p->precision == PFFT_F32) {
+        std::vector<float> t(2 * (size_t)n);
+        for (int m = 0; m < n; m++) {
+            double a = 2.0 * M_PI * (double)m / (double)n;
+            t[2 * m] = (float)cos(a);
+            t[2 * m + 1] = (float)(-sin(a));
+        }
+        off = blob_put(p, t.data(), t.size() * 4);
+    } else {
+        std::vector<double> t(2 * (size_t)n);
+        for (int m = 0; m < n; m++) {
+            double a = 2.0 * M_PI * (double)m / (double)n;
+            t[2 * m] = cos(a);
+            t[2 * m + 1] = -sin(a);
+        }
+        off = blob_put(p, t.data(), t.size() * 8);
+    }
+    p->tw_cache[n] = {off, 0};
+    return off;
+}
+
+struct LineRec {
+    int32_t rank[2];
+    int64_t O[2], E[2], I[2];
+};
+
+// Enumerate every line of a stage along `axis` (source layout A, destination
+// layout B) and group them into tiles of at most W lines that are adjacent in
+// both layouts.
+static void build_tiles(pfft_plan_s *p, Launch &ln, int W)
+{
+    const Layout &A = p->layouts[ln.src];
+    const Layout &B = p->layouts[ln.dst];
+    const Layout *S[2] = {&A, &B};
+    const int nd = A.ndim, a = ln.axis;
+    // global extents of the non-transform axes; the two sides may differ in
+    // the transform axis only (real vs half-spectrum length)
+    int64_t ext[kMaxDims];
+    int64_t nlines = 1;
+    for (int m = 0; m < nd; m++) {
+        ext[m] = (m == a) ? 1 : A.shape[m];
+        nlines *= ext[m];
+    }
+    std::vector<LineRec> lines;
+    lines.reserve(nlines);
+    int64_t g[kMaxDims];
+    for (int64_t f = 0; f < nlines; f++) {
+        int64_t t = f;
+        for (int m = nd - 1; m >= 0; m--) {
+            g[m] = t % ext[m];
+            t /= ext[m];
+        }
+        LineRec rec;
+        for (int s = 0; s < 2; s++) {
+            const Layout &L = *S[s];
+            int64_t c[kMaxDims] = {};
+            for (int m = 0; m < nd; m++)
+                if (m != a && L.axis_dir[m] >= 0) c[L.axis_dir[m]] = L.own[m][g[m]];
+            int64_t rank = 0;
+            for (int i = 0; i < L.ngrid; i++) rank += c[i] * L.rstride[i];
+            int64_t O = 0, E = 1, I = 0;
+            for (int m = 0; m < a; m++) {
+                int64_t n = L.local_extent(m, L.axis_dir[m] >= 0 ? c[L.axis_dir[m]] : 0);
+                O = O * n + L.loc[m][g[m]];
+            }
+            for (int m = a + 1; m < nd; m++) {
+                int64_t n = L.local_extent(m, L.axis_dir[m] >= 0 ? c[L.axis_dir[m]] : 0);
+                I = I * n + L.loc[m][g[m]];
+                E *= n;
+            }
+            rec.rank[s] = (int32_t)rank;
+            rec.O[s] = O;
+            rec.E[s] = E;
+            rec.I[s] = I;
+        }
+        lines.push_back(rec);
+    }
+    const bool contig = ln.contig != 0;
+    auto less = [contig](const LineRec &x, const LineRec &y) {
+        if (x.rank[1] != y.rank[1]) return x.rank[1] < y.rank[1];
+        if (x.rank[0] != y.rank[0]) return x.rank[0] < y.rank[0];
+        if (x.E[1] != y.E[1]) return x.E[1] < y.E[1];
+        if (x.E[0] != y.E[0]) return x.E[0] < y.E[0];
+        if (contig) return x.O[1] < y.O[1];
+        if (x.O[1] != y.O[1]) return x.O[1] < y.O[1];
+        if (x.O[0] != y.O[0]) return x.O[0] < y.O[0];
+        return x.I[1] < y.I[1];
+    };
+    std::sort(lines.begin(), lines.end(), less);
+    std::vector<Tile> tiles;
+    for (size_t i = 0; i < lines.size();) {
+        const LineRec &h = lines[i];
+        Tile t;
+        memset(&t, 0, sizeof t);
+        for (int s = 0; s < 2; s++) {
+            t.rank[s] = h.rank[s];
+            t.O[s] = h.O[s];
+            t.E[s] = h.E[s];
+            t.I[s] = h.I[s];
+        }
+        int cnt = 1;
+        size_t k = i + 1;
+        while (k < lines.size() && cnt < W) {
+            const LineRec &x = lines[k];
+            bool ok = true;
+            for (int s = 0; s < 2 && ok; s++) {
+                if (x.rank[s] != h.rank[s] || x.E[s] != h.E[s]) ok = false;
+                else if (contig) ok = (x.O[s] == h.O[s] + cnt) && (x.I[s] == h.I[s]);
+                else ok = (x.O[s] == h.O[s]) && (x.I[s] == h.I[s] + cnt);
+            }
+            if (!ok) break;
+            cnt++;
+            k++;
+        }
+        t.count = cnt;
+        tiles.push_back(t);
+        i = k;
+    }
+    ln.ntiles = (int64_t)tiles.size();
+    ln.off_tiles = blob_put(p, tiles.data(), tiles.size() * sizeof(Tile));
+}
+
+static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs)
+{
+    Layout L;
+    L.init(p->ndim, shape, ngrid, grid, dirs);
+    p->layouts.push_back(std::move(L));
+    return (int)p->layouts.size() - 1;
+}
+
+static int finish_launch(pfft_plan_s *p, Launch &ln)
+{
+    const int prec = p->precision;
+    if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
+        return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
+    int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, &ln.cfg);
+    if (rc != 0)
+        return fail(PFFT_EUNSUPPORTED, "no kernel for length " + std::to_string(ln.N) +
+                                           (ln.contig ? " (contiguous)" : " (strided)"));
+    const int sides[2] = {ln.src, ln.dst};
+    for (int s = 0; s < 2; s++) side_tables(p, sides[s], ln.axis, &ln.off_pos[s], &ln.off_na[s], &ln.off_rank[s], &ln.R[s]);
+    if (ln.kind == KIND_C2C) {
+        ln.off_tw = twiddle_table(p, ln.N);
+    } else if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) {
+        ln.off_tw = twiddle_table(p, ln.N / 2 > 0 ? ln.N / 2 : 1);
+        ln.off_tw2 = twiddle_table(p, ln.N);
+    }
+    build_tiles(p, ln, ln.cfg.W);
+    return PFFT_OK;
+}
+
+static Launch make_copy(int src, int dst, int last_axis, int64_t n)
+{
+    Launch c;
+    c.kind = KIND_COPY;
+    c.axis = last_axis;
+    c.N = (int)n;
+    c.contig = 1;
+    c.src = src;
+    c.dst = dst;
+    return c;
+}
+
+// The redistribution from layout a to layout b as kernel launches, per the
+// plan's path flag.  Fused: none (the caller's transform gathers).  Unfused:
+// one copy.  Pack+realign: local transpose into per-destination contiguous
+// chunks, contiguous chunk exchange, realign on the receiving side
+// (Sec. 3.2.1, Eq. transpose).
+static int redistribution_launches(pfft_plan_s *p, int a, int b, std::vector<Launch> &out)
+{
+    // copies: add_layout below may reallocate p->layouts
+    const Layout A = p->layouts[a];
+    const Layout B = p->layouts[b];
+    const int nd = p->ndim;
+    unsigned path = p->flags & PFFT_PATH_MASK;
+    if (path == PFFT_PATH_PACK_REALIGN) {
+        // v: whole in A, split in B; w: split in A, whole in B; both by dir.
+        int v = -1, w = -1, n_diff = 0;
+        for (int m = 0; m < nd; m++) {
+            if (A.axis_dir[m] != B.axis_dir[m]) {
+                n_diff++;
+                if (A.axis_dir[m] < 0) v = m;
+                if (B.axis_dir[m] < 0) w = m;
+            }
+        }
+        if (n_diff == 2 && v >= 0 && w >= 0 && A.axis_dir[w] == B.axis_dir[v]) {
+            int dir = A.axis_dir[w];
+            int64_t grid2[kMaxDims];
+            for (int i = 0; i < A.ngrid; i++) grid2[i] = A.grid[i];
+            grid2[A.ngrid] = A.grid[dir];
+            int send_dirs[kMaxDims], recv_dirs[kMaxDims];
+            for (int m = 0; m < nd; m++) send_dirs[m] = recv_dirs[m] = A.axis_dir[m];
+            send_dirs[v] = A.ngrid;  // chunk index q innermost: contiguous per destination
+            recv_dirs[w] = A.ngrid;  // chunk index p innermost: contiguous per source
+            recv_dirs[v] = dir;
+            int ls = add_layout(p, A.shape, A.ngrid + 1, grid2, send_dirs);
+            int lr = add_layout(p, A.shape, A.ngrid + 1, grid2, recv_dirs);
+            int64_t n = A.shape[nd - 1];
+            out.push_back(make_copy(a, ls, nd - 1, n));
+            out.push_back(make_copy(ls, lr, nd - 1, n));
+            out.push_back(make_copy(lr, b, nd - 1, n));
+            return PFFT_OK;
+        }
+    }
+    out.push_back(make_copy(a, b, nd - 1, A.shape[nd - 1]));
+    return PFFT_OK;
+}
+
+// Build the launch list of one direction.  Each step is (src, li, dst, axis,
+// kind): the data sit in layout src, the partial transform along `axis` is
+// the one the chain performs on layout li (where the axis is whole), and its
+// result must end in layout dst.  R2C reads the real layout src directly into
+// li; C2R writes the real layout dst directly from li.
+static int build_direction(pfft_plan_s *p, const std::vector<std::array<int, 5>> &steps, int sign,
+                           std::vector<Launch> &out)
+{
+    const bool fused = (p->flags & PFFT_PATH_MASK) == PFFT_PATH_FUSED;
+    for (const auto &st : steps) {
+        int src = st[0], li = st[1], dst = st[2], axis = st[3], kind = st[4];
+        int tsrc = src, tdst = dst;
+        if (!fused) {
+            if (kind != KIND_R2C && src != li) {
+                int rc = redistribution_launches(p, src, li, out);
+                if (rc) return rc;
+                tsrc = li;
+            }
+            if (kind != KIND_C2R) tdst = li;
+        }
+        Launch ln;
+        ln.kind = kind;
+        ln.axis = axis;
+        ln.contig = axis == p->ndim - 1;
+        ln.src = tsrc;
+        ln.dst = tdst;
+        ln.sign = sign;
+        ln.scale_axis = axis;
+        if (kind == KIND_R2C) ln.N = (int)p->layouts[tsrc].shape[axis];
+        else if (kind == KIND_C2R) ln.N = (int)p->layouts[tdst].shape[axis];
+        else ln.N = (int)p->layouts[tdst].shape[axis];
+        out.push_back(ln);
+        if (!fused && kind != KIND_C2R && tdst != dst) {
+            int rc = redistribution_launches(p, tdst, dst, out);
+            if (rc) return rc;
+        }
+    }
+    for (auto &ln : out) {
+        int rc = finish_launch(p, ln);
+        if (rc) return rc;
+    }
+    return PFFT_OK;
+}
+
+static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
+{
+    const int nd = p->ndim, ng = p->ngrid;
+    std::array<int, kMaxDims> dirs;
+    dirs.fill(-1);
+    for (int i = 0; i < ng; i++) dirs[i] = i;
+    p->dirs.push_back(dirs);
+    if (chain == nullptr) {
+        // paper's rule: step t = 1..g moves direction g-t from axis g-t to g-t+1
+        for (int t = 1; t <= ng; t++) {
+            int i = ng - t;
+            dirs[i] = -1;
+            dirs[i + 1] = i;
+            p->dirs.push_back(dirs);
+        }
+    } else {
+        for (int s = 0; s < nsteps; s++) {
+            int d = chain[2 * s], na = chain[2 * s + 1];
+            if (d < 0 || d >= ng || na < 0 || na >= nd) return fail(PFFT_EGRID, "chain step out of range");
+            if (dirs[na] != -1) return fail(PFFT_EGRID, "chain step onto a distributed axis");
+            int old = -1;
+            for (int m = 0; m < nd; m++)
+                if (dirs[m] == d) old = m;
+            if (old < 0) return fail(PFFT_EINTERNAL, "lost grid direction");
+            dirs[old] = -1;
+            dirs[na] = d;
+            p->dirs.push_back(dirs);
+        }
+    }
+    p->nlayouts = (int)p->dirs.size();
+    // forward schedule: on each layout, every newly whole axis, highest first
+    bool done[kMaxDims] = {};
+    for (int li = 0; li < p->nlayouts; li++)
+        for (int m = nd - 1; m >= 0; m--)
+            if (p->dirs[li][m] < 0 && !done[m]) {
+                p->sched.push_back({li, m});
+                done[m] = true;
+            }
+    for (int m = 0; m < nd; m++)
+        if (!done[m]) return fail(PFFT_EGRID, "chain leaves axis " + std::to_string(m) + " distributed everywhere");
+    if (p->kind == PFFT_R2C && (p->sched[0].first != 0 || p->sched[0].second != nd - 1))
+        return fail(PFFT_EGRID, "r2c needs the last axis whole in the input layout");
+
+    int64_t spec[kMaxDims];
+    for (int m = 0; m < nd; m++) spec[m] = p->shape[m];
+    if (p->kind == PFFT_R2C) spec[nd - 1] = p->shape[nd - 1] / 2 + 1;
+    for (int li = 0; li < p->nlayouts; li++) add_layout(p, spec, ng, p->grid, p->dirs[li].data());
+    if (p->kind == PFFT_R2C) p->real0 = add_layout(p, p->shape, ng, p->grid, p->dirs[0].data());
+    p->elem = p->precision == PFFT_F32 ? 8 : 16;
+    p->spec_bytes = (size_t)p->layouts[0].total() * p->elem;
+
+    const int last = p->nlayouts - 1;
+    const int K = (int)p->sched.size();
+    // forward: stage k reads where stage k-1 wrote; the last writes the last layout
+    std::vector<std::array<int, 5>> fsteps, bsteps;
+    int where = (p->kind == PFFT_R2C) ? p->real0 : 0;
+    for (int k = 0; k < K; k++) {
+        int li = p->sched[k].first, axis = p->sched[k].second;
+        int dst = (k == K - 1) ? last : li;
+        int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : KIND_C2C;
+        fsteps.push_back({where, li, dst, axis, kind});
+        where = dst;
+    }
+    where = last;
+    for (int k = 0; k < K; k++) {
+        int li = p->sched[K - 1 - k].first, axis = p->sched[K - 1 - k].second;
+        int dst = (k == K - 1) ? 0 : li;
+        int kind = KIND_C2C;
+        if (k == K - 1 && p->kind == PFFT_R2C) {
+            kind = KIND_C2R;
+            dst = p->real0;
+        }
+        bsteps.push_back({where, li, dst, axis, kind});
+        where = dst;
+    }
+    int rc;
+    if (!(p->flags & PFFT_LAYOUTS_ONLY)) {
+        rc = build_direction(p, fsteps, -1, p->fwd);
+        if (rc) return rc;
+        rc = build_direction(p, bsteps, +1, p->bwd);
+        if (rc) return rc;
+    }
+    // standalone redistributions between chain neighbours
+    for (int li = 0; li + 1 < p->nlayouts; li++) {
+        Launch u = make_copy(li, li + 1, nd - 1, spec[nd - 1]);
+        Launch d = make_copy(li + 1, li, nd - 1, spec[nd - 1]);
+        rc = finish_launch(p, u);
+        if (rc) return rc;
+        rc = finish_launch(p, d);
+        if (rc) return rc;
+        p->up.push_back(u);
+        p->down.push_back(d);
+    }
+    return PFFT_OK;
+}
+
+static double axis_scale(const pfft_plan_s *p, int axis, bool forward_factors)
+{
+    if (axis < 0) return 1.0;
+    double n = (double)p->shape[axis];
+    if (p->norm == PFFT_NORM_FORWARD) return forward_factors ? 1.0 / n : 1.0;
+    if (p->norm == PFFT_NORM_BACKWARD) return forward_factors ? 1.0 : 1.0 / n;
+    return 1.0;
+}
+
+static hipEvent_t pool_event(pfft_plan_s *p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Algorithmic bytes of a launch: its source read once plus its destination
+// written once.
+static double launch_bytes(const pfft_plan_s *p, const Launch &ln)
+{
+    auto esz = [p](int lid) { return (double)(lid == p->real0 ? p->elem / 2 : p->elem); };
+    return (double)p->layouts[ln.src].total() * esz(ln.src) + (double)p->layouts[ln.dst].total() * esz(ln.dst);
+}
+
+static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
+                      int flags, hipStream_t stream, int direction = 4)
+{
+    if (ln.ntiles == 0) return PFFT_OK;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (p->profiling) {
+        ea = pool_event(p);
+        eb = pool_event(p);
+        if (!ea || !eb) return fail(PFFT_EHIP, "hipEventCreate failed");
+        if (hipEventRecord(ea, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
+    }
+    const uint8_t *dev = (const uint8_t *)p->dev;
+    StageArgs a;
+    memset(&a, 0, sizeof a);
+    a.src = src;
+    a.dst = dst;
+    for (int s = 0; s < 2; s++) {
+        a.side[s].rank_off = (const int64_t *)(dev + ln.off_rank[s]);
+        a.side[s].pos = (const int2 *)(dev + ln.off_pos[s]);
+        a.side[s].na = (const int32_t *)(dev + ln.off_na[s]);
+        a.side[s].R = ln.R[s];
+    }
+    a.tiles = (const Tile *)(dev + ln.off_tiles);
+    a.twiddle = dev + ln.off_tw;
+    a.twiddle2 = dev + ln.off_tw2;
+    a.ntiles = ln.ntiles;
+    a.scale = scale;
+    a.N = ln.N;
+    a.flags = flags;
+    size_t esize = p->elem;
+    if (ln.kind == KIND_COPY && (ln.src == p->real0 || ln.dst == p->real0)) esize = p->elem / 2;
+    int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, esize, a, stream);
+    if (rc != 0) return fail(PFFT_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+    if (p->profiling) {
+        if (hipEventRecord(eb, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
+        p->prof.push_back({ln.kind, ln.axis, ln.contig, ln.N, direction, launch_bytes(p, ln), ea, eb});
+    }
+    return PFFT_OK;
+}
+
+// Run a launch list with ping-pong buffers so the last launch writes `out`.
+// mode 0: forward factors from norm on forward, 1: backward factors.
+static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out, void *work,
+                    bool forward_factors, int sign, int r2c_flags, hipStream_t stream, int direction)
+{
+    if (p->flags & PFFT_LAYOUTS_ONLY) return fail(PFFT_EUNSUPPORTED, "plan was created with PFFT_LAYOUTS_ONLY");
+    if (!p->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
+    if (!in || !out) return fail(PFFT_EINVAL, "null buffer");
+    const int n = (int)list.size();
+    if (n > 1 && !work) return fail(PFFT_EINVAL, "null workspace");
+    uint8_t *w0 = (uint8_t *)work;
+    uint8_t *w1 = w0 ? w0 + ((p->spec_bytes + 255) & ~(size_t)255) : nullptr;
+    const void *cur = in;
+    // does the final launch write a real layout (c2r)? then intermediates can't use out
+    bool out_is_real = (list.back().dst == p->real0);
+    int parity = 0;
+    for (int k = 0; k < n; k++) {
+        const Launch &ln = list[k];
+        void *dst;
+        if (k == n - 1) {
+            dst = out;
+        } else if (out_is_real) {
+            dst = (parity++ % 2 == 0) ? (void *)w0 : (void *)w1;
+        } else {
+            dst = ((n - 1 - k) % 2 == 0) ? out : (void *)w0;
+        }
+        double scale = (ln.kind == KIND_COPY) ? 1.0 : axis_scale(p, ln.scale_axis, forward_factors);
+        int flags = 0;
+        if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) flags = r2c_flags;
+        int rc = run_launch(p, ln, cur, dst, scale, sign, flags, stream, direction);
+        if (rc) return rc;
+        cur = dst;
+    }
+    return PFFT_OK;
+}
+
+// Host emulation of the address arithmetic every kernel of a launch performs:
+// all reads and writes must stay inside their buffers and every destination
+// element must be written exactly once.
+static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *what)
+{
+    const Layout &A = p->layouts[ln.src];
+    const Layout &B = p->layouts[ln.dst];
+    const Layout *S[2] = {&A, &B};
+    const int64_t size[2] = {A.total(), B.total()};
+    // positions per side along the axis (real side of R2C/C2R is N real values)
+    int64_t npos[2] = {A.shape[ln.axis], B.shape[ln.axis]};
+    std::vector<uint8_t> hits((size_t)size[1], 0);
+    const Tile *tiles = (const Tile *)(p->blob.data() + ln.off_tiles);
+    if (ln.ntiles >= ((int64_t)1 << 31)) return fail(PFFT_EINTERNAL, std::string(what) + ": grid too large");
+    for (int64_t ti = 0; ti < ln.ntiles; ti++) {
+        const Tile &t = tiles[ti];
+        if (t.count < 1 || t.count > ln.cfg.W) return fail(PFFT_EINTERNAL, std::string(what) + ": tile count");
+        for (int s = 0; s < 2; s++) {
+            const Layout &L = *S[s];
+            const int32_t *pos = (const int32_t *)(p->blob.data() + ln.off_pos[s]);
+            const int32_t *na = (const int32_t *)(p->blob.data() + ln.off_na[s]);
+            const int64_t *roff = (const int64_t *)(p->blob.data() + ln.off_rank[s]);
+            for (int w = 0; w < t.count; w++) {
+                for (int64_t j = 0; j < npos[s]; j++) {
+                    int c = pos[2 * j], loc = pos[2 * j + 1];
+                    int64_t rank = t.rank[s] + (int64_t)c * ln.R[s];
+                    if (rank < 0 || rank >= L.P) return fail(PFFT_EINTERNAL, std::string(what) + ": rank");
+                    int64_t O = t.O[s] + (ln.contig ? w : 0), I = t.I[s] + (ln.contig ? 0 : w);
+                    int64_t addr = roff[rank] + (O * na[c] + loc) * t.E[s] + I;
+                    if (addr < roff[rank] || addr >= roff[rank + 1] || addr >= size[s])
+                        return fail(PFFT_EINTERNAL, std::string(what) + ": address out of its block");
+                    if (s == 1) {
+                        if (hits[addr] == 255) return fail(PFFT_EINTERNAL, std::string(what) + ": overflow");
+                        hits[addr]++;
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t e = 0; e < size[1]; e++)
+        if (hits[e] != 1) return fail(PFFT_EINTERNAL, std::string(what) + ": destination element written " +
+                                                          std::to_string(hits[e]) + " times");
+    return PFFT_OK;
+}
+
+}  // namespace pfft
+
+// ------------------------------------------------------------------ C ABI --
+
+#define PFFT_GUARD_BEGIN try {
+#define PFFT_GUARD_END                                                    \
+    }                                                                     \
+    catch (const std::bad_alloc &) {                                      \
+        return pfft::fail(PFFT_EINTERNAL, "host allocation failed");      \
+    }                                                                     \
+    catch (...) {                                                         \
+        return pfft::fail(PFFT_EINTERNAL, "unexpected exception");        \
+    }
+
+extern "C" {
+
+int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim, const int *grid_dims,
+                     int precision, int kind, int norm, const int *chain, int nsteps, unsigned flags)
+{
+    PFFT_GUARD_BEGIN
+    if (!out) return fail(PFFT_EINVAL, "null plan pointer");
+    *out = nullptr;
+    if (!global_shape || !grid_dims) return fail(PFFT_EINVAL, "null shape or grid");
+    if (ndim < 1 || ndim > PFFT_MAX_DIMS) return fail(PFFT_ESHAPE, "ndim out of range");
+    if (grid_ndim < 1 || grid_ndim >= ndim) return fail(PFFT_EGRID, "grid dims must be in [1, ndim)");
+    for (int m = 0; m < ndim; m++)
+        if (global_shape[m] < 1 || global_shape[m] > (int64_t)1 << 31) return fail(PFFT_ESHAPE, "bad extent");
+    int64_t P = 1;
+    for (int i = 0; i < grid_ndim; i++) {
+        if (grid_dims[i] < 1) return fail(PFFT_EGRID, "grid extent < 1");
+        P *= grid_dims[i];
+    }
+    if (P > (int64_t)1 << 20) return fail(PFFT_EGRID, "too many virtual ranks");
+    if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
+    if (kind != PFFT_C2C && kind != PFFT_R2C) return fail(PFFT_EDTYPE, "bad kind");
+    if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
+    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY)) != 0 || (flags & PFFT_PATH_MASK) == 3u)
+        return fail(PFFT_EINVAL, "bad flags");
+    if (chain && nsteps < 0) return fail(PFFT_EINVAL, "bad nsteps");
+    int64_t total = 1;
+    for (int m = 0; m < ndim; m++) total *= global_shape[m];
+    if (total > ((int64_t)1 << 40)) return fail(PFFT_ESHAPE, "array too large");
+    pfft_plan_s *p = new pfft_plan_s();
+    p->ndim = ndim;
+    for (int m = 0; m < ndim; m++) p->shape[m] = global_shape[m];
+    p->ngrid = grid_ndim;
+    for (int i = 0; i < grid_ndim; i++) p->grid[i] = grid_dims[i];
+    p->precision = precision;
+    p->kind = kind;
+    p->norm = norm;
+    p->flags = flags;
+    int rc = build_plan(p, chain, chain ? nsteps : 0);
+    if (rc != PFFT_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_plan_destroy(pfft_plan plan)
+{
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    for (auto &r : plan->prof) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : plan->pool) hipEventDestroy(e);
+    delete plan;
+    return PFFT_OK;
+}
+
+int pfft_set_profiling(pfft_plan plan, int enable)
+{
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    plan->profiling = enable != 0;
+    return PFFT_OK;
+}
+
+int pfft_profile_read(pfft_plan plan, int max_entries, pfft_profile_entry *entries, int *n)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan || !n || (max_entries > 0 && !entries)) return fail(PFFT_EINVAL, "null argument");
+    int k = 0;
+    int status = PFFT_OK;
+    for (auto &r : plan->prof) {
+        if (k < max_entries) {
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess) status = fail(PFFT_EHIP, std::string("profile read: ") + hipGetErrorString(e));
+            pfft_profile_entry &o = entries[k];
+            o.kind = r.kind;
+            o.axis = r.axis;
+            o.contig = r.contig;
+            o.length = r.N;
+            o.direction = r.direction;
+            o.ms = ms;
+            o.bytes = r.bytes;
+        }
+        k++;
+        plan->pool.push_back(r.a);
+        plan->pool.push_back(r.b);
+    }
+    plan->prof.clear();
+    *n = k;
+    return status;
+    PFFT_GUARD_END
+}
+
+int pfft_num_layouts(pfft_plan plan, int *n)
+{
+    if (!plan || !n) return fail(PFFT_EINVAL, "null argument");
+    *n = plan->nlayouts;
+    return PFFT_OK;
+}
+
+int pfft_local_block(pfft_plan plan, int layout, int real, int rank, int64_t *shape, int64_t *start,
+                     int64_t *offset)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan || !shape || !start || !offset) return fail(PFFT_EINVAL, "null argument");
+    if (layout < 0 || layout >= plan->nlayouts) return fail(PFFT_EINVAL, "layout out of range");
+    int lid = layout;
+    if (real) {
+        if (plan->kind != PFFT_R2C || layout != 0) return fail(PFFT_EINVAL, "only layout 0 of an r2c plan is real");
+        lid = plan->real0;
+    }
+    const Layout &L = plan->layouts[lid];
+    if (rank < 0 || rank >= L.P) return fail(PFFT_EINVAL, "rank out of range");
+    L.block(rank, shape, start);
+    *offset = L.rank_off[rank];
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_buffer_bytes(pfft_plan plan, int layout, int real, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(PFFT_EINVAL, "null argument");
+    if (layout < 0 || layout >= plan->nlayouts) return fail(PFFT_EINVAL, "layout out of range");
+    if (real) {
+        if (plan->kind != PFFT_R2C || layout != 0) return fail(PFFT_EINVAL, "only layout 0 of an r2c plan is real");
+        *bytes = (size_t)plan->layouts[plan->real0].total() * (plan->elem / 2);
+        return PFFT_OK;
+    }
+    *bytes = (size_t)plan->layouts[layout].total() * plan->elem;
+    return PFFT_OK;
+}
+
+int pfft_device_state_bytes(pfft_plan plan, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(PFFT_EINVAL, "null argument");
+    *bytes = (plan->blob.size() + 255) & ~(size_t)255;
+    return PFFT_OK;
+}
+
+int pfft_bind_device_state(pfft_plan plan, void *dev, hipStream_t stream)
+{
+    if (!plan || !dev) return fail(PFFT_EINVAL, "null argument");
+    if (((uintptr_t)dev & 255u) != 0) return fail(PFFT_EINVAL, "device state must be 256-byte aligned");
+    hipError_t e = hipMemcpyAsync(dev, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(PFFT_EHIP, std::string("upload: ") + hipGetErrorString(e));
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(PFFT_EHIP, std::string("upload sync: ") + hipGetErrorString(e));
+    plan->dev = dev;
+    return PFFT_OK;
+}
+
+int pfft_workspace_bytes(pfft_plan plan, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(PFFT_EINVAL, "null argument");
+    size_t one = (plan->spec_bytes + 255) & ~(size_t)255;
+    *bytes = plan->kind == PFFT_R2C ? 2 * one : one;
+    return PFFT_OK;
+}
+
+int pfft_redistribute(pfft_plan plan, int layout_from, int layout_to, const void *in, void *out, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan || !in || !out) return fail(PFFT_EINVAL, "null argument");
+    if (!plan->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
+    int n = plan->nlayouts;
+    if (layout_from < 0 || layout_from >= n || layout_to < 0 || layout_to >= n)
+        return fail(PFFT_EINVAL, "layout out of range");
+    if (layout_to == layout_from + 1) return run_launch(plan, plan->up[layout_from], in, out, 1.0, -1, 0, stream);
+    if (layout_to == layout_from - 1) return run_launch(plan, plan->down[layout_to], in, out, 1.0, -1, 0, stream);
+    return fail(PFFT_EINVAL, "layouts must be chain neighbours (one exchange apart)");
+    PFFT_GUARD_END
+}
+
+int pfft_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    return run_list(plan, plan->fwd, in, out, work, true, -1, 0, stream, 0);
+    PFFT_GUARD_END
+}
+
+int pfft_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    return run_list(plan, plan->bwd, in, out, work, false, +1, 0, stream, 1);
+    PFFT_GUARD_END
+}
+
+int pfft_adjoint_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    return run_list(plan, plan->bwd, in, out, work, true, +1, SF_HALVE_INTERIOR, stream, 2);
+    PFFT_GUARD_END
+}
+
+int pfft_adjoint_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    return run_list(plan, plan->fwd, in, out, work, false, -1, SF_DOUBLE_INTERIOR, stream, 3);
+    PFFT_GUARD_END
+}
+
+int pfft_validate_plan(pfft_plan plan)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan) return fail(PFFT_EINVAL, "null plan");
+    const std::vector<Launch> *lists[4] = {&plan->fwd, &plan->bwd, &plan->up, &plan->down};
+    const char *names[4] = {"forward", "backward", "redistribute up", "redistribute down"};
+    for (int li = 0; li < 4; li++)
+        for (const Launch &ln : *lists[li]) {
+            int rc = validate_launch(plan, ln, names[li]);
+            if (rc) return rc;
+        }
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+const char *pfft_strerror(int status)
+{
+    switch (status) {
+    case PFFT_OK: return "ok";
+    case PFFT_EINVAL: return "invalid argument";
+    case PFFT_ESHAPE: return "bad global shape";
+    case PFFT_EGRID: return "bad virtual process grid or chain";
+    case PFFT_EDTYPE: return "bad precision or kind";
+    case PFFT_EUNSUPPORTED: return "unsupported transform length";
+    case PFFT_EWORKSPACE: return "device state not bound or buffer too small";
+    case PFFT_EHIP: return "HIP runtime error";
+    case PFFT_EINTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+const char *pfft_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

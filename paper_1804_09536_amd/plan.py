@@ -1,0 +1,201 @@
+"""Python face of libpfft: a ``Plan`` holding a C plan, its device state and
+workspace, with methods that pass torch tensors' device pointers and the
+current HIP stream to the C ABI.  PyTorch supplies device memory and streams
+only; every step of the transform runs in libpfft's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import PATHS, NORMS, check
+
+_DT = {
+    ("c2c", "f32"): (torch.complex64, torch.complex64),
+    ("c2c", "f64"): (torch.complex128, torch.complex128),
+    ("r2c", "f32"): (torch.float32, torch.complex64),
+    ("r2c", "f64"): (torch.float64, torch.complex128),
+}
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """A distributed multidimensional FFT over a virtual process grid.
+
+    shape: global array shape (the real shape for kind="r2c").
+    grid: virtual process grid dims (1 <= len(grid) < len(shape)).
+    precision: "f32" (complex64) or "f64" (complex128).
+    kind: "c2c" or "r2c".  norm: "forward" (the paper's), "backward", "none".
+    chain: None for the paper's rule, else [(grid_dir, new_axis), ...].
+    path: "fused" (redistribution fused into the transform's load),
+          "unfused" (standalone redistribution kernel) or "pack_realign"
+          (local transpose + contiguous exchange + realign).
+    layouts_only: plan layouts and redistributions only (any lengths); the
+          transforms then raise.
+    """
+
+    def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
+                 norm: str = "forward", chain=None, path: str = "fused", device=None,
+                 layouts_only: bool = False):
+        lib = _lib.load()
+        self.shape = tuple(int(x) for x in shape)
+        self.grid = tuple(int(x) for x in grid)
+        self.precision, self.kind, self.norm, self.path = precision, kind, norm, path
+        self.chain = None if chain is None else [tuple(int(v) for v in s) for s in chain]
+        self.device = torch.device(device if device is not None else "cuda")
+        self.in_dtype, self.spec_dtype = _DT[(kind, precision)]
+        h = ctypes.c_void_p()
+        shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
+        grd = (ctypes.c_int * len(self.grid))(*self.grid)
+        if self.chain is None:
+            ch, nsteps = None, 0
+        else:
+            flat = [v for s in self.chain for v in s]
+            ch, nsteps = (ctypes.c_int * max(1, len(flat)))(*flat), len(self.chain)
+        st = lib.pfft_plan_create(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd,
+                                  0 if precision == "f32" else 1, 0 if kind == "c2c" else 1, NORMS[norm],
+                                  ch, nsteps, PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0))
+        check(st, "pfft_plan_create")
+        self._h = h
+        n = ctypes.c_int()
+        check(lib.pfft_num_layouts(h, ctypes.byref(n)), "pfft_num_layouts")
+        self.num_layouts = n.value
+        self._state = None
+        self._work = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.pfft_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ layouts --
+    def local_block(self, layout: int, rank: int, real: bool = False):
+        lib = _lib.load()
+        nd = len(self.shape)
+        shp = (ctypes.c_int64 * nd)()
+        sta = (ctypes.c_int64 * nd)()
+        off = ctypes.c_int64()
+        check(lib.pfft_local_block(self._h, layout, int(real), rank, shp, sta, ctypes.byref(off)),
+              "pfft_local_block")
+        return tuple(shp), tuple(sta), off.value
+
+    def buffer_numel(self, layout: int, real: bool = False) -> int:
+        lib = _lib.load()
+        b = ctypes.c_size_t()
+        check(lib.pfft_buffer_bytes(self._h, layout, int(real), ctypes.byref(b)), "pfft_buffer_bytes")
+        esize = torch.empty(0, dtype=self.in_dtype if real else self.spec_dtype).element_size()
+        return b.value // esize
+
+    def device_state_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        check(_lib.load().pfft_device_state_bytes(self._h, ctypes.byref(b)), "pfft_device_state_bytes")
+        return b.value
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        check(_lib.load().pfft_workspace_bytes(self._h, ctypes.byref(b)), "pfft_workspace_bytes")
+        return b.value
+
+    def validate(self):
+        """Host emulation of every kernel's addressing (bounds, write-once)."""
+        check(_lib.load().pfft_validate_plan(self._h), "pfft_validate_plan")
+        return self
+
+    def set_profiling(self, enable: bool = True):
+        check(_lib.load().pfft_set_profiling(self._h, int(enable)), "pfft_set_profiling")
+
+    def profile_read(self, max_entries: int = 65536):
+        """Per-launch records of the calls since the last read (waits for them)."""
+        buf = (_lib.ProfileEntry * max_entries)()
+        n = ctypes.c_int()
+        check(_lib.load().pfft_profile_read(self._h, max_entries, buf, ctypes.byref(n)), "pfft_profile_read")
+        kinds = {0: "c2c", 1: "copy", 2: "r2c", 3: "c2r"}
+        return [dict(kind=kinds.get(e.kind, "?"), axis=e.axis, contig=bool(e.contig), length=e.length,
+                     direction=e.direction, ms=e.ms, bytes=e.bytes) for e in buf[:min(n.value, max_entries)]]
+
+    # ----------------------------------------------------- device binding --
+    def bind(self):
+        """Allocate (through torch) and upload the plan's device tables."""
+        if self._state is None:
+            nbytes = max(256, self.device_state_bytes())
+            self._state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            check(_lib.load().pfft_bind_device_state(self._h, _ptr(self._state), _stream_handle(self.device)),
+                  "pfft_bind_device_state")
+        return self
+
+    def workspace(self) -> torch.Tensor:
+        if self._work is None:
+            nbytes = max(256, self.workspace_bytes())
+            self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def empty(self, layout: int, real: bool = False) -> torch.Tensor:
+        dt = self.in_dtype if real else self.spec_dtype
+        return torch.empty(self.buffer_numel(layout, real), dtype=dt, device=self.device)
+
+    # ---------------------------------------------------------- transforms --
+    def _check_in(self, x: torch.Tensor, layout: int, real: bool):
+        dt = self.in_dtype if real else self.spec_dtype
+        if x.dtype != dt:
+            raise TypeError("expected %s, got %s" % (dt, x.dtype))
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("expected a contiguous device tensor")
+        if x.numel() != self.buffer_numel(layout, real):
+            raise ValueError("expected %d elements, got %d" % (self.buffer_numel(layout, real), x.numel()))
+
+    def _run(self, fn, x, out, work, in_real, out_real, in_layout, out_layout, name):
+        self.bind()
+        self._check_in(x, in_layout, in_real)
+        if out is None:
+            out = self.empty(out_layout, out_real)
+        else:
+            self._check_in(out, out_layout, out_real)
+        if work is None:
+            work = self.workspace()
+        check(fn(self._h, _ptr(x), _ptr(out), _ptr(work), _stream_handle(self.device)), name)
+        return out
+
+    def forward(self, x: torch.Tensor, out=None, work=None) -> torch.Tensor:
+        lib = _lib.load()
+        r = self.kind == "r2c"
+        return self._run(lib.pfft_forward, x, out, work, r, False, 0, self.num_layouts - 1, "pfft_forward")
+
+    def backward(self, x: torch.Tensor, out=None, work=None) -> torch.Tensor:
+        lib = _lib.load()
+        r = self.kind == "r2c"
+        return self._run(lib.pfft_backward, x, out, work, False, r, self.num_layouts - 1, 0, "pfft_backward")
+
+    def adjoint_forward(self, x: torch.Tensor, out=None, work=None) -> torch.Tensor:
+        lib = _lib.load()
+        r = self.kind == "r2c"
+        return self._run(lib.pfft_adjoint_forward, x, out, work, False, r, self.num_layouts - 1, 0,
+                         "pfft_adjoint_forward")
+
+    def adjoint_backward(self, x: torch.Tensor, out=None, work=None) -> torch.Tensor:
+        lib = _lib.load()
+        r = self.kind == "r2c"
+        return self._run(lib.pfft_adjoint_backward, x, out, work, r, False, 0, self.num_layouts - 1,
+                         "pfft_adjoint_backward")
+
+    def redistribute(self, x: torch.Tensor, layout_from: int, layout_to: int, out=None) -> torch.Tensor:
+        lib = _lib.load()
+        self.bind()
+        self._check_in(x, layout_from, False)
+        if out is None:
+            out = self.empty(layout_to)
+        else:
+            self._check_in(out, layout_to, False)
+        check(lib.pfft_redistribute(self._h, layout_from, layout_to, _ptr(x), _ptr(out),
+                                    _stream_handle(self.device)), "pfft_redistribute")
+        return out

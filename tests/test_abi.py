@@ -1,0 +1,95 @@
+"""Host-side checks of libpfft (no GPU needed): the library loads and exports
+every function include/pfft.h declares, plans describe the same layouts as
+the oracle, and bad arguments come back as error codes."""
+import ctypes
+
+import pytest
+
+import oracle
+from paper_1804_09536_amd import _lib
+
+
+def test_library_exports_every_header_function():
+    lib = _lib.load()
+    names = _lib.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+LAYOUT_CASES = [
+    ((512, 512, 512), (8, 8), None, "c2c"),
+    ((256, 256, 256), (4, 4), None, "c2c"),
+    ((32, 32, 32), (4,), [(0, 2)], "c2c"),
+    ((64, 64, 64, 64), (2, 2, 4), None, "c2c"),
+    ((512, 512, 512), (8, 8), None, "r2c"),
+    ((42, 127, 256), (3, 4), None, "c2c"),
+    ((5, 7, 6), (2, 3), None, "c2c"),
+    ((3, 2, 4), (4, 3), None, "c2c"),
+    ((16, 32, 8), (3, 5), None, "c2c"),       # uneven splits, power-of-two lengths
+    ((4, 2, 8), (8, 3), None, "c2c"),         # empty blocks
+    ((8, 16, 4, 32), (3, 1, 5), None, "c2c"),
+]
+
+
+@pytest.mark.parametrize("shape,grid,chain,kind", LAYOUT_CASES)
+def test_plan_layouts_match_oracle(shape, grid, chain, kind):
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan(shape, grid, kind=kind, chain=chain, layouts_only=True)
+    ch = oracle.Chain.paper(shape, grid, kind=kind, steps=chain)
+    assert p.num_layouts == len(ch.dirs)
+    for li in range(p.num_layouts):
+        lay = ch.layout(li)
+        offs = lay.offsets()
+        for r in range(lay.nranks):
+            shp, st, off = p.local_block(li, r)
+            assert (shp, st) == lay.block(r)
+            assert off == offs[r]
+        assert p.buffer_numel(li) == offs[-1]
+    if kind == "r2c":
+        lay = ch.layout(0, spectral=False)
+        for r in range(lay.nranks):
+            shp, st, off = p.local_block(0, r, real=True)
+            assert (shp, st) == lay.block(r)
+
+
+def _create(shape, grid, prec=0, kind=0, norm=0, chain=None, flags=0):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    shp = (ctypes.c_int64 * len(shape))(*shape)
+    grd = (ctypes.c_int * max(1, len(grid)))(*grid)
+    ch, n = None, 0
+    if chain is not None:
+        flat = [v for s in chain for v in s]
+        ch, n = (ctypes.c_int * max(1, len(flat)))(*flat), len(chain)
+    st = lib.pfft_plan_create(ctypes.byref(h), len(shape), shp, len(grid), grd, prec, kind, norm, ch, n, flags)
+    if st == 0:
+        lib.pfft_plan_destroy(h)
+    return st
+
+
+def test_error_codes():
+    assert _create((16, 16, 16), (2, 2)) == 0
+    assert _create((16, 16, 16), (2, 2, 2)) == -3        # grid dims must be < ndim
+    assert _create((16, 0, 16), (2, 2)) == -2           # empty axis
+    assert _create((16, 16, 16), (2, 0)) == -3          # empty grid direction
+    assert _create((16, 16, 16), (2, 2), prec=7) == -4
+    assert _create((16, 16, 16), (2, 2), kind=9) == -4
+    assert _create((16, 16, 16), (2, 2), norm=5) == -1
+    assert _create((16, 16, 16), (2, 2), flags=3) == -1
+    assert _create((16, 16, 16), (2,), chain=[(0, 0)]) == -3   # onto a distributed axis
+    assert _create((16, 16, 16), (2,), chain=[(3, 1)]) == -3   # no such direction
+    assert _create((16, 16, 16), (4,), chain=[]) == -3          # axis 0 never whole
+    assert _create((16, 16, 17), (2, 2)) == -5                  # no kernel for length 17 yet
+    assert _create((16, 16, 17), (2, 2), flags=4) == 0          # layouts only: any length
+
+
+def test_calls_before_binding_fail_cleanly():
+    lib = _lib.load()
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan((16, 16, 16), (2, 2))
+    st = lib.pfft_forward(p._h, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), None)
+    assert st == -6
+    assert lib.pfft_forward(None, None, None, None, None) == -1
+    assert lib.pfft_redistribute(p._h, 0, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -6
+    assert _lib.strerror(-5) == "unsupported transform length"

@@ -1,0 +1,129 @@
+"""GPU parity of the complex path against the FP64 oracle: redistribution
+bit for bit, forward / backward transforms within the relative L2 tolerance
+of the precision (1e-5 for complex64, 1e-12 for complex128)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_09536_amd import inputs
+from paper_1804_09536_amd.plan import Plan
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+NPDT = {"f32": np.complex64, "f64": np.complex128}
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+REDIST = [
+    ((64, 48, 40), (8, 8), None, "f32"),
+    ((16, 32, 8), (3, 5), None, "f32"),
+    ((5, 7, 6), (2, 3), None, "f64"),
+    ((3, 2, 4), (4, 3), None, "f32"),          # empty blocks
+    ((6, 5, 4, 7), (2, 2, 3), None, "f32"),    # 4-D, three exchanges
+    ((8, 6, 10), (4,), [(0, 2)], "f64"),       # slab, axis 0 -> axis 2
+    ((33, 17, 257), (8, 8), None, "f32"),      # ragged everywhere
+]
+
+
+@pytest.mark.parametrize("shape,grid,chain,prec", REDIST)
+def test_redistribute_bit_exact(shape, grid, chain, prec):
+    print("case", shape, grid, chain, prec, flush=True)
+    p = Plan(shape, grid, precision=prec, chain=chain, layouts_only=True)
+    ch = oracle.Chain.paper(shape, grid, steps=chain)
+    n = p.buffer_numel(0)
+    payload = inputs.index_payload(n, NPDT[prec])
+    for li in range(p.num_layouts - 1):
+        x = _to_dev(payload)
+        out = p.empty(li + 1)
+        out.fill_(complex(float("nan"), float("nan")))
+        y = p.redistribute(x, li, li + 1, out=out)
+        expect = oracle.redistribute(payload, ch.layout(li), ch.layout(li + 1))
+        got = _host(y)
+        assert got.tobytes() == expect.tobytes()
+        back = _host(p.redistribute(y, li + 1, li))
+        assert back.tobytes() == payload.tobytes()
+
+
+C2C = [
+    ((32, 32, 32), (4,), [(0, 2)], "f64"),     # the small slab workload, axis 0 <-> 2
+    ((64, 32, 16), (4, 4), None, "f32"),
+    ((16, 32, 8), (3, 5), None, "f32"),        # uneven pencils
+    ((4, 2, 8), (8, 3), None, "f64"),          # empty blocks
+    ((16, 32, 8, 64), (2, 2, 4), None, "f32"),  # 4-D on a 3-D grid
+    ((128, 64, 32), (2,), None, "f32"),        # slab, paper rule
+    ((8, 8, 8), (1, 1), None, "f32"),
+    ((2, 4, 4096), (2, 2), None, "f32"),       # long contiguous lines
+    ((1024, 4, 2), (2, 1), None, "f64"),       # long strided lines
+    ((256, 256, 256), (4, 4), None, "f32"),    # the 256^3 pencil workload
+]
+
+
+@pytest.mark.parametrize("shape,grid,chain,prec", C2C)
+def test_c2c_matches_oracle(shape, grid, chain, prec):
+    print("case", shape, grid, chain, prec, flush=True)
+    p = Plan(shape, grid, precision=prec, chain=chain)
+    ch = oracle.Chain.paper(shape, grid, steps=chain)
+    n = p.buffer_numel(0)
+    u = inputs.uniform_complex(n, [1, n], NPDT[prec])
+    x = _to_dev(u)
+    y = p.forward(x)
+    got = _host(y)
+    expect = oracle.forward(ch, u.astype(np.complex128))
+    assert relerr(got, expect) <= TOL[prec]
+    # the backward alone, on the GPU's own forward output
+    z = _host(p.backward(y))
+    expect_b = oracle.backward(ch, got.astype(np.complex128))
+    assert relerr(z, expect_b) <= TOL[prec]
+    assert relerr(z, u.astype(np.complex128)) <= TOL[prec]
+    # the input is never written
+    assert _host(x).tobytes() == u.tobytes()
+
+
+@pytest.mark.parametrize("norm", ["backward", "none"])
+def test_c2c_other_norms(norm):
+    shape, grid = (32, 16, 64), (2, 4)
+    p = Plan(shape, grid, norm=norm)
+    ch = oracle.Chain.paper(shape, grid, norm=norm)
+    n = p.buffer_numel(0)
+    u = inputs.uniform_complex(n, [2], np.complex64)
+    got = _host(p.forward(_to_dev(u)))
+    assert relerr(got, oracle.forward(ch, u.astype(np.complex128))) <= 1e-5
+    z = _host(p.backward(_to_dev(got)))
+    assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= 1e-5
+
+
+@pytest.mark.parametrize("path", ["unfused", "pack_realign"])
+@pytest.mark.parametrize("shape,grid,prec", [((32, 16, 64), (2, 4), "f32"), ((16, 32, 8), (3, 5), "f64"),
+                                            ((8, 16, 4, 32), (3, 1, 5), "f32")])
+def test_other_paths_match(path, shape, grid, prec):
+    print("case", path, shape, grid, prec, flush=True)
+    p = Plan(shape, grid, precision=prec, path=path)
+    ch = oracle.Chain.paper(shape, grid)
+    n = p.buffer_numel(0)
+    u = inputs.uniform_complex(n, [3, n], NPDT[prec])
+    got = _host(p.forward(_to_dev(u)))
+    assert relerr(got, oracle.forward(ch, u.astype(np.complex128))) <= TOL[prec]
+    z = _host(p.backward(_to_dev(got)))
+    assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= TOL[prec]
+
+
+def test_deterministic():
+    p = Plan((64, 32, 16), (4, 4))
+    u = inputs.uniform_complex(p.buffer_numel(0), [4], np.complex64)
+    a = _host(p.forward(_to_dev(u)))
+    b = _host(p.forward(_to_dev(u)))
+    assert a.tobytes() == b.tobytes()
