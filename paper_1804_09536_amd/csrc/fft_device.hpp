@@ -144,6 +144,20 @@ __device__ __forceinline__ void dft_regs(T2 *a)
         T2 t = a[0];
         a[0] = c_add(t, a[1]);
         a[1] = c_sub(t, a[1]);
+    } else if constexpr (R == 3) {
+        using T = decltype(a[0].x);
+        const T s3 = (T)(SIGN * 0.86602540378443864676);  // SIGN * sqrt(3)/2
+        const T2 p = c_add(a[1], a[2]);
+        const T2 m = c_sub(a[1], a[2]);
+        T2 t;
+        t.x = a[0].x - (T)0.5 * p.x;
+        t.y = a[0].y - (T)0.5 * p.y;
+        T2 u;  // i * s3 * m
+        u.x = -s3 * m.y;
+        u.y = s3 * m.x;
+        a[0] = c_add(a[0], p);
+        a[1] = c_add(t, u);
+        a[2] = c_sub(t, u);
     } else {
         constexpr int H = R / 2;
         T2 e[H], o[H];
@@ -159,14 +173,25 @@ __device__ __forceinline__ void dft_regs(T2 *a)
 }
 
 // ---------------------------------------------------------------------------
-// Radix plan of an N-point line (N a power of two, 2 <= N <= 4096).  Each
-// thread of a line owns P points; every pass has radix R dividing P.
+// Radix plan of an N-point line, N = 2^a or 3 * 2^a (2 <= N <= 4096 / 6144).
+// Each thread of a line owns P points; every pass has a radix dividing P.
+// Radix-3 lengths run the power-of-two passes first and one radix-3 pass
+// last, so the span L of every pass is a power of two.
 
-__host__ __device__ constexpr int fft_points(int N) { return N <= 16 ? N : (N <= 512 ? 8 : 16); }
+__host__ __device__ constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
-__host__ __device__ constexpr int fft_npasses(int N)
+__host__ __device__ constexpr int pow2_part(int N) { return is_pow2(N) ? N : N / 3; }
+
+__host__ __device__ constexpr int fft_points_pow2(int N) { return N <= 16 ? N : (N <= 512 ? 8 : 16); }
+
+__host__ __device__ constexpr int fft_points(int N)
 {
-    int P = fft_points(N), n = 0, rem = N;
+    return is_pow2(N) ? fft_points_pow2(N) : 3 * (N == 3 ? 1 : fft_points_pow2(N / 3));
+}
+
+__host__ __device__ constexpr int fft_npasses_pow2(int N)
+{
+    int P = fft_points_pow2(N), n = 0, rem = N;
     while (rem > 1) {
         rem = rem >= P ? rem / P : 1;
         n++;
@@ -174,9 +199,16 @@ __host__ __device__ constexpr int fft_npasses(int N)
     return n;
 }
 
+__host__ __device__ constexpr int fft_npasses(int N)
+{
+    return is_pow2(N) ? fft_npasses_pow2(N) : fft_npasses_pow2(N / 3) + 1;
+}
+
 __host__ __device__ constexpr int fft_radix(int N, int pass)
 {
-    int P = fft_points(N), rem = N;
+    const int N2 = pow2_part(N);
+    if (!is_pow2(N) && pass == fft_npasses(N) - 1) return 3;
+    int P = fft_points_pow2(N2), rem = N2;
     for (int i = 0; i < pass; i++) rem = rem >= P ? rem / P : 1;
     return rem >= P ? P : rem;
 }
@@ -186,6 +218,11 @@ __host__ __device__ constexpr int fft_span(int N, int pass)  // L = product of r
     int L = 1;
     for (int i = 0; i < pass; i++) L *= fft_radix(N, i);
     return L;
+}
+
+__host__ __device__ constexpr bool fft_supported(int N)
+{
+    return N >= 2 && (is_pow2(N) ? N <= 4096 : (N % 3 == 0 && is_pow2(N / 3) && N <= 6144));
 }
 
 // Butterflies of one pass on the P registers of one line slot.  Register m

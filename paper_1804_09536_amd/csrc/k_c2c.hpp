@@ -25,7 +25,9 @@ struct C2CShape {
     static constexpr int VEC = (!CONTIG && sizeof(T) == 4) ? 2 : 1;  // lines per access
     static constexpr int ESZ = 2 * (int)sizeof(T);
     static constexpr int W0 = (fft_npasses(N) > 1) ? (64 * 1024) / (N * ESZ) : 128;
-    static constexpr int W = W0 > 64 && fft_npasses(N) > 1 ? 64 : (W0 < VEC ? VEC : W0);  // lines per tile
+    static constexpr int floor_pow2(int x) { return x < 2 ? 1 : 2 * floor_pow2(x / 2); }
+    static constexpr int W1 = floor_pow2(W0 > 64 && fft_npasses(N) > 1 ? 64 : W0);
+    static constexpr int W = W1 < VEC ? VEC : W1;  // lines per tile
     static constexpr int nl_for(int nl) { return (TPL * W / nl > 512 && nl < W) ? nl_for(nl * 2) : nl; }
     static constexpr int NL = nl_for(VEC);  // lines per thread
     static constexpr int SLOTS = W / NL;    // line slots per pass

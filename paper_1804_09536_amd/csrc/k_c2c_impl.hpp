@@ -31,8 +31,9 @@ static void c2c_cfg_n(int contig, KernelConfig *c)
     c->id = 0;
 }
 
-#define PFFT_FOR_EACH_N(X) \
-    X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define PFFT_FOR_EACH_N(X)                                                                          \
+    X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(3) X(6) X(12) X(24) \
+        X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
 
 template <typename T>
 static int c2c_config_t(int N, int contig, KernelConfig *cfg)

@@ -1,14 +1,220 @@
-// k_real.hip -- real-to-complex / complex-to-real stage kernels (placeholder
-// until the half-length packing kernels land).
+// k_real.hip -- real-to-complex and complex-to-real stage kernels along the
+// last axis (the half spectrum k = 0..N/2 of a real line, footnote of Sec. 2).
+//
+// A real line of even length N = 2M is read as M complex points
+// z_n = x_{2n} + i x_{2n+1}; one M-point complex transform Z and a pairing of
+// bins k and M-k then give the N/2+1 output bins:
+//   X_k = (Z_k + conj Z_{M-k}) / 2 - (i/2) e^{-2 pi i k/N} (Z_k - conj Z_{M-k}).
+// The complex-to-real kernel inverts this: with imag(X_0) = imag(X_M) = 0,
+//   Z'_k = (X_k + conj X_{M-k}) + i e^{+2 pi i k/N} (X_k - conj X_{M-k}),
+// an M-point inverse transform of Z' gives x_{2n} + i x_{2n+1}, i.e. the sum
+// over the Hermitian extension of X (unnormalised).
+// Flags turn them into each other's adjoints: SF_DOUBLE_INTERIOR doubles the
+// r2c output bins 0 < k < M; SF_HALVE_INTERIOR halves the c2r input bins.
+#include "fft_device.hpp"
+#include "k_c2c.hpp"
 #include "pfft_kernels.hpp"
 
 namespace pfft {
 
-int real_config(int, int, int, KernelConfig *) { return -1; }
+template <typename T2, int M>
+struct RealLds {
+    static constexpr int LINE = M + M / 8 + 2;
+    __device__ static __forceinline__ int idx(int w, int k) { return w * LINE + k + (k >> 3); }
+};
 
-hipError_t real_launch(int, int, int, const KernelConfig &, const StageArgs &, hipStream_t)
+template <typename T, int NR, int KIND>
+__global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageArgs a)
 {
-    return hipErrorInvalidValue;
+    using T2 = typename V2<T>::type;
+    constexpr int M = NR / 2;
+    using S = C2CShape<T, M, true>;
+    constexpr int P = S::P, TPL = S::TPL, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
+    using LT = LdsTile<T2, M, W, true>;
+    using RL = RealLds<T2, M>;
+    constexpr int LDS_N = (LT::SIZE > W * RL::LINE) ? LT::SIZE : W * RL::LINE;
+    __shared__ T2 lds[LDS_N];
+
+    const Tile &t = a.tiles[blockIdx.x];
+    const int count = t.count;
+    const int tid = threadIdx.x;
+    const int jt = tid % TPL;
+    const int slot = tid / TPL;
+    int wl[NL];
+    bool valid[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+        wl[l] = slot + l * SLOTS;
+        valid[l] = wl[l] < count;
+    }
+    const T2 *__restrict__ tw = (const T2 *)a.twiddle;    // M-point table
+    const T2 *__restrict__ tw2 = (const T2 *)a.twiddle2;  // N-point table
+    const T scale = (T)a.scale;
+    T2 v[NL][P];
+
+    if constexpr (KIND == KIND_R2C) {
+        // real side: pairs (2n, 2n+1) of real positions, n = jt + m*TPL
+        SideAddr<P> rs;
+        rs.init(a.side[0], t, 0, 2 * jt, 2 * TPL, NR, true);
+        const T *__restrict__ in = (const T *)a.src;
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++)
+                v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
+        fft_passes<T2, M, W, true, -1, NL, 0>(v, wl, jt, lds, tw);
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) lds[RL::idx(wl[l], jt + m * TPL)] = v[l][m];
+        __syncthreads();
+        SideAddr<P> cs;
+        cs.init(a.side[1], t, 1, jt, TPL, M + 1, true);
+        T2 *__restrict__ out = (T2 *)a.dst;
+        const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            if (!valid[l]) continue;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const T2 zk = lds[RL::idx(wl[l], k)];
+                T2 zc = lds[RL::idx(wl[l], (M - k) & (M - 1))];
+                zc.y = -zc.y;
+                const T2 e = c_scale(c_add(zk, zc), (T)0.5);
+                T2 d = c_sub(zk, zc);  // (Z_k - conj Z_{M-k})
+                T2 o;                  // -(i/2) d
+                o.x = d.y * (T)0.5;
+                o.y = -d.x * (T)0.5;
+                T2 x = c_add(e, c_mul(tw2[k], o));
+                T f = scale;
+                if (dbl && k > 0) f *= (T)2;
+                out[cs.off[m] + wl[l] * cs.stride[m]] = c_scale(x, f);
+            }
+            if (jt == 0) {
+                // bin M: E_0 - O_0 = Re Z_0 - Im Z_0
+                const T2 z0 = lds[RL::idx(wl[l], 0)];
+                const Side &sd = a.side[1];
+                const int2 pc = sd.pos[M];
+                const long na = sd.na[pc.x];
+                const long base = sd.rank_off[t.rank[1] + pc.x * sd.R];
+                const long addr = base + ((long)(t.O[1] + wl[l]) * na + pc.y) * t.E[1] + t.I[1];
+                T2 x;
+                x.x = (z0.x - z0.y) * scale;
+                x.y = (T)0;
+                out[addr] = x;
+            }
+        }
+    } else {
+        // complex side: bins k = jt + m*TPL and bin M, through LDS
+        const T2 *__restrict__ in = (const T2 *)a.src;
+        SideAddr<P> cs;
+        cs.init(a.side[0], t, 0, jt, TPL, M + 1, true);
+        const bool half = (a.flags & SF_HALVE_INTERIOR) != 0;
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                T2 x = valid[l] ? in[cs.off[m] + wl[l] * cs.stride[m]] : c_zero<T2>();
+                if (k == 0) x.y = (T)0;
+                if (half && k > 0) x = c_scale(x, (T)0.5);
+                lds[RL::idx(wl[l], k)] = x;
+            }
+            if (jt == 0) {
+                T2 x = c_zero<T2>();
+                if (valid[l]) {
+                    const Side &sd = a.side[0];
+                    const int2 pc = sd.pos[M];
+                    const long na = sd.na[pc.x];
+                    const long base = sd.rank_off[t.rank[0] + pc.x * sd.R];
+                    const long addr = base + ((long)(t.O[0] + wl[l]) * na + pc.y) * t.E[0] + t.I[0];
+                    x = in[addr];
+                }
+                x.y = (T)0;
+                lds[RL::idx(wl[l], M)] = x;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const T2 xk = lds[RL::idx(wl[l], k)];
+                T2 xc = lds[RL::idx(wl[l], M - k)];
+                xc.y = -xc.y;
+                const T2 s = c_add(xk, xc);
+                const T2 d = c_sub(xk, xc);
+                T2 w = tw2[k];
+                w.y = -w.y;             // e^{+2 pi i k / N}
+                const T2 wd = c_mul(w, d);
+                T2 z;                   // s + i * wd
+                z.x = s.x - wd.y;
+                z.y = s.y + wd.x;
+                v[l][m] = z;
+            }
+        __syncthreads();
+        fft_passes<T2, M, W, true, 1, NL, 0>(v, wl, jt, lds, tw);
+        SideAddr<P> rs;
+        rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
+        T *__restrict__ out = (T *)a.dst;
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++)
+                if (valid[l]) *(T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]) = c_scale(v[l][m], scale);
+    }
+}
+
+#define PFFT_FOR_EACH_NR(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+
+template <typename T>
+static int real_config_t(int NR, KernelConfig *cfg)
+{
+    switch (NR) {
+#define PFFT_CASE(n)                                 \
+    case n:                                          \
+        cfg->W = C2CShape<T, n / 2, true>::W;        \
+        cfg->threads = C2CShape<T, n / 2, true>::NT; \
+        cfg->id = 0;                                 \
+        return 0;
+        PFFT_FOR_EACH_NR(PFFT_CASE)
+#undef PFFT_CASE
+    default:
+        return -1;
+    }
+}
+
+template <typename T>
+static hipError_t real_launch_t(int NR, int kind, const StageArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.ntiles);
+    switch (NR) {
+#define PFFT_CASE(n)                                                                   \
+    case n:                                                                            \
+        if (kind == KIND_R2C)                                                          \
+            hipLaunchKernelGGL((k_real<T, n, KIND_R2C>), grid, dim3(C2CShape<T, n / 2, true>::NT), 0, s, a); \
+        else                                                                           \
+            hipLaunchKernelGGL((k_real<T, n, KIND_C2R>), grid, dim3(C2CShape<T, n / 2, true>::NT), 0, s, a); \
+        return hipGetLastError();
+        PFFT_FOR_EACH_NR(PFFT_CASE)
+#undef PFFT_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+int real_config(int prec, int N, int kind, KernelConfig *cfg)
+{
+    (void)kind;
+    return prec == 0 ? real_config_t<float>(N, cfg) : real_config_t<double>(N, cfg);
+}
+
+hipError_t real_launch(int prec, int N, int kind, const KernelConfig &, const StageArgs &a, hipStream_t s)
+{
+    return prec == 0 ? real_launch_t<float>(N, kind, a, s) : real_launch_t<double>(N, kind, a, s);
 }
 
 }  // namespace pfft
