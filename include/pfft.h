@@ -69,6 +69,9 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_PATH_UNFUSED 1u      /* standalone redistribution kernel, then transform in place of the new layout */
 #define PFFT_PATH_PACK_REALIGN 2u /* traditional method: local transpose, contiguous exchange, realign (Sec. 3.2.1) */
 #define PFFT_PATH_MASK 3u
+#define PFFT_PLACE_SCATTER 8u     /* fused path: each partial transform writes its result straight into the
+                                     layout of the next one (redistribution fused into the store) instead of
+                                     its own layout (fused into the next load); same results */
 #define PFFT_LAYOUTS_ONLY 4u      /* plan layouts and redistributions only: no transform kernels are
                                      set up (any lengths), pfft_forward & co. return PFFT_EUNSUPPORTED */
 
@@ -99,7 +102,7 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *     before the step).  Initially direction i splits axis i.
  *   nsteps: number of chain steps (ignored when chain is NULL).
  *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
- *     or-ed with PFFT_LAYOUTS_ONLY.
+ *     or-ed with PFFT_PLACE_SCATTER and PFFT_LAYOUTS_ONLY.
  * The chain must leave every axis transformed (each axis whole in some
  * layout).  For PFFT_R2C the last axis must be whole in layout 0.
  * Returns PFFT_OK and *out, or an error (then *out is NULL).
@@ -107,6 +110,27 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim,
                      const int *grid_dims, int precision, int kind, int norm, const int *chain,
                      int nsteps, unsigned flags);
+
+/*
+ * Performance knobs of a plan (results never change).  tile_*: 0 default
+ * lines per tile, 1 half as many (more workgroups per CU), 2 twice as many
+ * (wider coalesced rows, more LDS), 3 twice as many exchanged through the
+ * default LDS in two portions (wider rows at the default LDS size; lengths
+ * without this shape use the default); resident_*: 1 launches only as many
+ * workgroups as the device holds at once, each looping over tiles, 0 one
+ * workgroup per tile.  *_contig applies to partial transforms along the last
+ * axis, *_strided to the others.  pfft_plan_set_tuning rebuilds the plan's
+ * tables: query pfft_device_state_bytes again and bind again before use.
+ */
+typedef struct {
+    int tile_contig;
+    int tile_strided;
+    int resident_contig;
+    int resident_strided;
+} pfft_tuning;
+
+int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);
+int pfft_plan_get_tuning(pfft_plan plan, pfft_tuning *tuning);
 
 /* Destroy a plan (host memory).  The caller frees the device state. */
 int pfft_plan_destroy(pfft_plan plan);

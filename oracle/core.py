@@ -36,7 +36,7 @@ __all__ = [
     "transform_schedule", "scatter_global", "gather_global", "redistribute",
     "redistribute_pairs", "fft_axis", "dft1", "bruteforce_dftn", "forward",
     "backward", "adjoint_forward", "adjoint_backward", "wavenumber_weight",
-    "loss_and_grad", "Chain",
+    "loss_and_grad", "Chain", "dft_bins", "layout_offset",
 ]
 
 
@@ -83,6 +83,9 @@ def _load():
         lib.oracle_c2r_last.restype = ctypes.c_int
         lib.oracle_bruteforce_dft.argtypes = [ctypes.c_int, i64p, vp, vp, ctypes.c_int, ctypes.c_double]
         lib.oracle_bruteforce_dft.restype = None
+        lib.oracle_dft_bins.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int64, i64p, vp, ctypes.c_int,
+                                        ctypes.c_double]
+        lib.oracle_dft_bins.restype = None
         _lib = lib
     return _lib
 
@@ -276,6 +279,43 @@ def bruteforce_dftn(glob: np.ndarray, sign: int, scale: float) -> np.ndarray:
     y = np.empty_like(x)
     _load().oracle_bruteforce_dft(x.ndim, _i64(x.shape), _ptr(x), _ptr(y), int(sign), float(scale))
     return y
+
+
+def dft_bins(glob: np.ndarray, bins, sign: int, scale: float) -> np.ndarray:
+    """Selected bins of Eq. multifft, each as the full sum over the array."""
+    x = np.ascontiguousarray(glob, dtype=np.complex128)
+    ks = np.ascontiguousarray(np.asarray(bins, dtype=np.int64).reshape(-1, x.ndim))
+    out = np.empty(len(ks), dtype=np.complex128)
+    _load().oracle_dft_bins(x.ndim, _i64(x.shape), _ptr(x), len(ks), ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            _ptr(out), int(sign), float(scale))
+    return out
+
+
+def layout_offset(lay: Layout, g) -> int:
+    """Position of global index g in a layout's buffer (found by searching
+    each split axis's parts)."""
+    nd = len(lay.shape)
+    coords = [0] * max(1, len(lay.grid))
+    loc = [0] * nd
+    for m in range(nd):
+        d = lay.axis_dir[m]
+        if d < 0:
+            loc[m] = int(g[m])
+            continue
+        for p in range(lay.grid[d]):
+            n, s = decompose(lay.shape[m], lay.grid[d], p)
+            if s <= g[m] < s + n:
+                coords[d] = p
+                loc[m] = int(g[m]) - s
+                break
+    rank = 0
+    for i, c in enumerate(coords[:len(lay.grid)]):
+        rank = rank * lay.grid[i] + c
+    ls, _ = lay.block(rank)
+    off = 0
+    for m in range(nd):
+        off = off * ls[m] + loc[m]
+    return lay.offsets()[rank] + off
 
 
 def _r2c_last(buf, lay_real: Layout, scale):

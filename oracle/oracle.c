@@ -533,3 +533,53 @@ void oracle_bruteforce_dft(int ndim, const int64_t *shape, const double *in, dou
         out[2 * kf + 1] = si * scale;
     }
 }
+
+/*
+ * Selected bins of the d-dimensional DFT, each evaluated as the full sum of
+ * Eq. multifft over every input element (no FFT): for bin k,
+ *   out_k = scale * sum_j in_j * prod_m e^{sign 2 pi i (k_m j_m mod N_m) / N_m}.
+ * ks holds nk multi-indices (ndim each).  The per-axis factors are tabulated
+ * once per bin; the sum runs in parallel over the leading axis.  O(total) per
+ * bin, so it can check single outputs of arrays far too large to brute-force.
+ */
+void oracle_dft_bins(int ndim, const int64_t *shape, const double *in, int64_t nk, const int64_t *ks,
+                     double *out, int sign, double scale)
+{
+    int64_t total = 1;
+    for (int m = 0; m < ndim; m++) total *= shape[m];
+    int64_t inner = total / shape[0];
+    double *tab[OMAXD];
+    for (int m = 0; m < ndim; m++) tab[m] = (double *)malloc((size_t)(2 * shape[m]) * sizeof(double));
+    for (int64_t b = 0; b < nk; b++) {
+        const int64_t *k = ks + b * ndim;
+        for (int m = 0; m < ndim; m++)
+            for (int64_t j = 0; j < shape[m]; j++) twiddle((k[m] * j) % shape[m], shape[m], sign, &tab[m][2 * j], &tab[m][2 * j + 1]);
+        double sr = 0.0, si = 0.0;
+#pragma omp parallel for reduction(+ : sr, si) schedule(static)
+        for (int64_t j0 = 0; j0 < shape[0]; j0++) {
+            double ar = 0.0, ai = 0.0;
+            for (int64_t r = 0; r < inner; r++) {
+                /* product of the factors of axes 1..d-1 */
+                int64_t t = r;
+                double wr = 1.0, wi = 0.0;
+                for (int m = ndim - 1; m >= 1; m--) {
+                    int64_t jm = t % shape[m];
+                    t /= shape[m];
+                    double xr = tab[m][2 * jm], xi = tab[m][2 * jm + 1];
+                    double nr = wr * xr - wi * xi;
+                    wi = wr * xi + wi * xr;
+                    wr = nr;
+                }
+                const double *u = in + 2 * (j0 * inner + r);
+                ar += u[0] * wr - u[1] * wi;
+                ai += u[0] * wi + u[1] * wr;
+            }
+            double xr = tab[0][2 * j0], xi = tab[0][2 * j0 + 1];
+            sr += ar * xr - ai * xi;
+            si += ar * xi + ai * xr;
+        }
+        out[2 * b] = sr * scale;
+        out[2 * b + 1] = si * scale;
+    }
+    for (int m = 0; m < ndim; m++) free(tab[m]);
+}

@@ -18,8 +18,14 @@ PFFT_F32, PFFT_F64 = 0, 1
 NORMS = {"forward": 0, "backward": 1, "none": 2}
 PATHS = {"fused": 0, "unfused": 1, "pack_realign": 2}
 PFFT_LAYOUTS_ONLY = 4
+PFFT_PLACE_SCATTER = 8
 
 _lib = None
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_contig", ctypes.c_int), ("tile_strided", ctypes.c_int),
+                ("resident_contig", ctypes.c_int), ("resident_strided", ctypes.c_int)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -52,6 +58,8 @@ def load():
         "pfft_plan_create": [ctypes.POINTER(vp), c_int, i64p, c_int, ip, c_int, c_int, c_int, ip, c_int,
                              ctypes.c_uint],
         "pfft_plan_destroy": [vp],
+        "pfft_plan_set_tuning": [vp, ctypes.POINTER(Tuning)],
+        "pfft_plan_get_tuning": [vp, ctypes.POINTER(Tuning)],
         "pfft_validate_plan": [vp],
         "pfft_num_layouts": [vp, ip],
         "pfft_local_block": [vp, c_int, c_int, c_int, i64p, i64p, i64p],

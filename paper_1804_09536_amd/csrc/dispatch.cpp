@@ -1,12 +1,25 @@
 // dispatch.cpp -- routes a stage to its kernel family.
+#include <mutex>
+#include <unordered_map>
+
 #include "pfft_kernels.hpp"
 
 namespace pfft {
 
-int kernel_config(int kind, int prec, int N, int contig, KernelConfig *cfg)
+int resident_workgroups(const void *kernel, int nt)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    return cus * per_cu;
+}
+
+int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConfig *cfg)
 {
     switch (kind) {
-    case KIND_C2C: return prec == 0 ? c2c_config_f32(N, contig, cfg) : c2c_config_f64(N, contig, cfg);
+    case KIND_C2C:
+        return prec == 0 ? c2c_config_f32(N, contig, variant, cfg) : c2c_config_f64(N, contig, variant, cfg);
     case KIND_COPY: return copy_config(N, cfg);
     case KIND_R2C:
     case KIND_C2R:

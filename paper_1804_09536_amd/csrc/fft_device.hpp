@@ -284,8 +284,10 @@ struct LdsTile {
 // Run all passes of an N-point transform on the register sets of NL line
 // slots (lines w_l of the tile), staging through LDS between passes.  On
 // entry register m of slot l holds point jt + m*TPL of line w_l; on exit the
-// transform's output point jt + m*TPL.
-template <typename T2, int N, int W, bool CONTIG, int SIGN, int NL, int PASS>
+// transform's output point jt + m*TPL.  The LDS holds WL lines: with H > 1
+// portions, slots [h*NL/H, (h+1)*NL/H) (lines [h*WL, (h+1)*WL)) exchange in
+// turn, so a tile of H*WL lines needs the LDS of WL lines.
+template <typename T2, int N, int WL, bool CONTIG, int SIGN, int NL, int H, int PASS>
 __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int (&wl)[NL], int jt, T2 *lds,
                                            const T2 *__restrict__ tw)
 {
@@ -294,25 +296,30 @@ __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int
     constexpr int R = fft_radix(N, PASS);
     constexpr int L = fft_span(N, PASS);
     constexpr int TPL = N / P;
-    using LT = LdsTile<T2, N, W, CONTIG>;
+    constexpr int NLH = NL / H;
+    static_assert(NL % H == 0, "portions must split the line slots evenly");
+    using LT = LdsTile<T2, N, WL, CONTIG>;
 #pragma unroll
     for (int l = 0; l < NL; l++) pass_butterflies<T2, N, P, R, L, SIGN>(v[l], jt, tw);
     if constexpr (PASS + 1 < NP) {
-        if constexpr (PASS > 0) __syncthreads();
 #pragma unroll
-        for (int l = 0; l < NL; l++) {
+        for (int h = 0; h < H; h++) {
+            if (PASS > 0 || h > 0) __syncthreads();
 #pragma unroll
-            for (int b = 0; b < P / R; b++)
+            for (int l = h * NLH; l < (h + 1) * NLH; l++) {
 #pragma unroll
-                for (int s = 0; s < R; s++)
-                    lds[LT::idx(wl[l], pass_out_index<N, P, R, L>(jt, b, s))] = v[l][b + s * (P / R)];
+                for (int b = 0; b < P / R; b++)
+#pragma unroll
+                    for (int s = 0; s < R; s++)
+                        lds[LT::idx(wl[l] - h * WL, pass_out_index<N, P, R, L>(jt, b, s))] = v[l][b + s * (P / R)];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int l = h * NLH; l < (h + 1) * NLH; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l] - h * WL, jt + m * TPL)];
         }
-        __syncthreads();
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l], jt + m * TPL)];
-        fft_passes<T2, N, W, CONTIG, SIGN, NL, PASS + 1>(v, wl, jt, lds, tw);
+        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1>(v, wl, jt, lds, tw);
     }
 }
 
@@ -328,6 +335,21 @@ struct SideAddr {
     {
         const int rank = t.rank[s];
         const long O = t.O[s], E = t.E[s], I = t.I[s];
+        if (sd.ublock > 0) {
+            // every block has the same shape: block index and offsets by arithmetic
+            const int un = sd.un;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                int j = jt + m * TPL;
+                if (j >= N) j = N - 1;
+                const int c = (unsigned)j / (unsigned)un;
+                const int loc = j - c * un;
+                const long base = (long)(rank + c * sd.R) * sd.ublock;
+                off[m] = (int)(base + (O * un + loc) * E + I);
+                stride[m] = contig ? (int)(un * E) : 1;
+            }
+            return;
+        }
 #pragma unroll
         for (int m = 0; m < P; m++) {
             int j = jt + m * TPL;

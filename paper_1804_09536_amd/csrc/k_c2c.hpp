@@ -1,7 +1,7 @@
 // k_c2c.hpp -- the complex partial-transform stage kernel (one template,
 // instantiated per precision in k_c2c_f32.hip / k_c2c_f64.hip).
 //
-// One workgroup transforms one tile of up to W lines of N points along the
+// A workgroup transforms tiles of up to W lines of N points along the
 // transform axis.  Each line is read from the source layout's rank blocks
 // (a line along an axis split over a grid direction is read from every rank
 // of that direction's subgroup: the subarray gather of the exchange) and
@@ -12,130 +12,197 @@
 // adjacent in memory, so lanes run across lines and every point of the tile
 // is a coalesced row of W elements; fp32 lanes move two lines per 16-byte
 // access.  Contiguous tiles (last axis): lanes run along the line.
+//
+// A workgroup walks the tile list with a stride of gridDim.x: launched with
+// one workgroup per tile it runs one tile; launched with the number of
+// workgroups the device holds at once it loops (a persistent grid).
 #pragma once
 
 #include "fft_device.hpp"
 
 namespace pfft {
 
-template <typename T, int N, bool CONTIG>
-struct C2CShape {
+template <typename T, int N, bool CONTIG, int W_, int NL_, int H_ = 1>
+struct C2CCfg {
     static constexpr int P = fft_points(N);
-    static constexpr int TPL = N / P;
+    static constexpr int TPL = N / P;                                // threads per line slot
     static constexpr int VEC = (!CONTIG && sizeof(T) == 4) ? 2 : 1;  // lines per access
+    static constexpr int W = W_;                                     // lines per tile
+    static constexpr int NL = NL_;                                   // lines per thread
+    static constexpr int SLOTS = W / NL;                             // line slots per pass
+    static constexpr int NT = TPL * SLOTS;                           // threads per workgroup
+    static constexpr int H = H_;                                     // LDS portions per exchange
+    static constexpr int WL = W / H;                                 // lines held in LDS at once
+    static_assert(W % NL == 0 && NL % VEC == 0, "tile shape");
+    static_assert(NL % H == 0 && W % H == 0 && (NL / H) % VEC == 0, "LDS portions");
+    static_assert(NT <= 1024, "workgroup too large");
+};
+
+// Default launch shape per (precision, N, mode): about 64-74 KB of LDS per
+// workgroup (two workgroups per CU), at most 512 threads.
+template <typename T, int N, bool CONTIG>
+struct C2CDefault {
+    static constexpr int VEC = (!CONTIG && sizeof(T) == 4) ? 2 : 1;
     static constexpr int ESZ = 2 * (int)sizeof(T);
+    static constexpr int TPL = N / fft_points(N);
     static constexpr int W0 = (fft_npasses(N) > 1) ? (64 * 1024) / (N * ESZ) : 128;
     static constexpr int floor_pow2(int x) { return x < 2 ? 1 : 2 * floor_pow2(x / 2); }
     static constexpr int W1 = floor_pow2(W0 > 64 && fft_npasses(N) > 1 ? 64 : W0);
-    static constexpr int W = W1 < VEC ? VEC : W1;  // lines per tile
+    static constexpr int W = W1 < VEC ? VEC : W1;
     static constexpr int nl_for(int nl) { return (TPL * W / nl > 512 && nl < W) ? nl_for(nl * 2) : nl; }
-    static constexpr int NL = nl_for(VEC);  // lines per thread
-    static constexpr int SLOTS = W / NL;    // line slots per pass
-    static constexpr int NT = TPL * SLOTS;  // threads per workgroup
-    static_assert(W % NL == 0 && NL % VEC == 0, "tile shape");
+    static constexpr int NL = nl_for(VEC);
+    using type = C2CCfg<T, N, CONTIG, W, NL>;
 };
 
-template <typename T, int N, bool CONTIG, int SIGN>
-__global__ __launch_bounds__((C2CShape<T, N, CONTIG>::NT)) void k_c2c(StageArgs a)
-{
+template <typename T, int N, bool CONTIG, int SIGN, class S>
+struct C2CWorker {
     using T2 = typename V2<T>::type;
     using T4 = typename V2<T>::quad;
-    using S = C2CShape<T, N, CONTIG>;
-    constexpr int P = S::P, TPL = S::TPL, VEC = S::VEC, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
-    using LT = LdsTile<T2, N, W, CONTIG>;
-    __shared__ T2 lds[(fft_npasses(N) > 1) ? LT::SIZE : 1];
+    static constexpr int P = S::P, TPL = S::TPL, VEC = S::VEC, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
+    using LT = LdsTile<T2, N, S::WL, CONTIG>;
+    static constexpr int LDS_SIZE = (fft_npasses(N) > 1) ? LT::SIZE : 1;
 
-    const Tile &t = a.tiles[blockIdx.x];
-    const int count = t.count;
-    const int tid = threadIdx.x;
     int jt, slot;
-    if constexpr (CONTIG) {
-        jt = tid % TPL;
-        slot = tid / TPL;
-    } else {
-        slot = tid % SLOTS;
-        jt = tid / SLOTS;
-    }
     int wl[NL];
+
+    // Make the thread geometry opaque to the optimiser once per tile, so the
+    // per-position LDS offsets and twiddle indices are recomputed instead of
+    // being hoisted out of the tile loop into (many) live registers.
+    __device__ __forceinline__ void refresh()
+    {
+        asm volatile("" : "+v"(jt));
 #pragma unroll
-    for (int l = 0; l < NL; l++) {
-        if constexpr (CONTIG)
-            wl[l] = slot + l * SLOTS;
-        else
-            wl[l] = (slot + (l / VEC) * SLOTS) * VEC + (l % VEC);
+        for (int l = 0; l < NL; l++) asm volatile("" : "+v"(wl[l]));
     }
 
-    SideAddr<P> src, dst;
-    src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
-    dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
-    const T2 *__restrict__ in = (const T2 *)a.src;
-    T2 *__restrict__ out = (T2 *)a.dst;
-    const T2 *__restrict__ tw = (const T2 *)a.twiddle;
+    __device__ __forceinline__ void init_geometry()
+    {
+        const int tid = threadIdx.x;
+        if constexpr (CONTIG) {
+            jt = tid % TPL;
+            slot = tid / TPL;
+        } else {
+            slot = tid % SLOTS;
+            jt = tid / SLOTS;
+        }
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            if constexpr (CONTIG)
+                wl[l] = slot + l * SLOTS;
+            else
+                wl[l] = (slot + (l / VEC) * SLOTS) * VEC + (l % VEC);
+        }
+    }
 
+    // Compute both sides' addresses of tile `ti` and issue its loads.  A full
+    // tile whose addresses are even on both sides (Tile flag bit 0) takes the
+    // unpredicated path; others are predicated line by line.
+    __device__ __forceinline__ void load(const StageArgs &a, long ti, T2 (&v)[NL][P], SideAddr<P> &dst,
+                                         int &count) const
+    {
+        const Tile &t = a.tiles[ti];
+        count = t.count;
+        const bool fast = (t.count == W) && (VEC == 1 || (t.flags & 1));
+        if (!fast) count = -count;  // sign marks the predicated path for process()
+        SideAddr<P> src;
+        src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
+        dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
+        const T2 *__restrict__ in = (const T2 *)a.src;
+        if (fast) {
+#pragma unroll
+            for (int l = 0; l < NL; l += VEC)
+#pragma unroll
+                for (int m = 0; m < P; m++) {
+                    if constexpr (VEC == 2) {
+                        T4 q = *(const T4 *)(in + src.off[m] + wl[l]);
+                        v[l][m].x = q.x;
+                        v[l][m].y = q.y;
+                        v[l + 1][m].x = q.z;
+                        v[l + 1][m].y = q.w;
+                    } else {
+                        v[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
+                    }
+                }
+        } else {
+            const int cnt = t.count;
+#pragma unroll
+            for (int l = 0; l < NL; l++) {
+                const bool ok = wl[l] < cnt;
+#pragma unroll
+                for (int m = 0; m < P; m++) v[l][m] = ok ? in[src.off[m] + wl[l] * src.stride[m]] : c_zero<T2>();
+            }
+        }
+    }
+
+    // Transform the registers of one tile (LDS-staged passes), scale, store.
+    __device__ __forceinline__ void process(const StageArgs &a, T2 (&v)[NL][P], const SideAddr<P> &dst, int count,
+                                            T2 *lds) const
+    {
+        if constexpr (fft_npasses(N) > 1) __syncthreads();  // the previous tile's last LDS reads are done
+        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, (const T2 *)a.twiddle);
+        const T scale = (T)a.scale;
+        if (scale != (T)1) {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++) v[l][m] = c_scale(v[l][m], scale);
+        }
+        T2 *__restrict__ out = (T2 *)a.dst;
+        if (count > 0) {
+#pragma unroll
+            for (int l = 0; l < NL; l += VEC)
+#pragma unroll
+                for (int m = 0; m < P; m++) {
+                    if constexpr (VEC == 2) {
+                        T4 q;
+                        q.x = v[l][m].x;
+                        q.y = v[l][m].y;
+                        q.z = v[l + 1][m].x;
+                        q.w = v[l + 1][m].y;
+                        *(T4 *)(out + dst.off[m] + wl[l]) = q;
+                    } else {
+                        out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+                    }
+                }
+        } else {
+            const int cnt = -count;
+#pragma unroll
+            for (int l = 0; l < NL; l++) {
+                const bool ok = wl[l] < cnt;
+#pragma unroll
+                for (int m = 0; m < P; m++)
+                    if (ok) out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+            }
+        }
+    }
+};
+
+// Occupancy target of a tile shape: two workgroups per CU when their LDS fits
+// (which caps VGPRs at 128 for 512-thread workgroups).
+template <class S>
+constexpr int c2c_waves_per_eu()
+{
+    return (S::NT == 512 && S::H > 1) ? 4 : 1;
+}
+
+template <typename T, int N, bool CONTIG, int SIGN, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c(
+    StageArgs a)
+{
+    using Wk = C2CWorker<T, N, CONTIG, SIGN, S>;
+    using T2 = typename Wk::T2;
+    constexpr int NL = S::NL, P = S::P;
+    __shared__ T2 lds[Wk::LDS_SIZE];
+    Wk wk;
+    wk.init_geometry();
+    const long G = gridDim.x, nt = a.ntiles;
     T2 v[NL][P];
-    bool valid[NL];
-#pragma unroll
-    for (int l = 0; l < NL; l++) valid[l] = wl[l] < count;
-    if constexpr (VEC == 2) {
-#pragma unroll
-        for (int l = 0; l < NL; l += 2) {
-#pragma unroll
-            for (int m = 0; m < P; m++) {
-                const int addr = src.off[m] + wl[l];
-                if (valid[l] && valid[l + 1] && (addr & 1) == 0) {
-                    T4 q = *(const T4 *)(in + addr);
-                    v[l][m].x = q.x;
-                    v[l][m].y = q.y;
-                    v[l + 1][m].x = q.z;
-                    v[l + 1][m].y = q.w;
-                } else {
-                    v[l][m] = valid[l] ? in[addr] : c_zero<T2>();
-                    v[l + 1][m] = valid[l + 1] ? in[addr + 1] : c_zero<T2>();
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++)
-                v[l][m] = valid[l] ? in[src.off[m] + wl[l] * src.stride[m]] : c_zero<T2>();
-    }
-
-    fft_passes<T2, N, W, CONTIG, SIGN, NL, 0>(v, wl, jt, lds, tw);
-
-    const T scale = (T)a.scale;
-    if (scale != (T)1) {
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++) v[l][m] = c_scale(v[l][m], scale);
-    }
-    if constexpr (VEC == 2) {
-#pragma unroll
-        for (int l = 0; l < NL; l += 2) {
-#pragma unroll
-            for (int m = 0; m < P; m++) {
-                const int addr = dst.off[m] + wl[l];
-                if (valid[l] && valid[l + 1] && (addr & 1) == 0) {
-                    T4 q;
-                    q.x = v[l][m].x;
-                    q.y = v[l][m].y;
-                    q.z = v[l + 1][m].x;
-                    q.w = v[l + 1][m].y;
-                    *(T4 *)(out + addr) = q;
-                } else {
-                    if (valid[l]) out[addr] = v[l][m];
-                    if (valid[l + 1]) out[addr + 1] = v[l + 1][m];
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++)
-                if (valid[l]) out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+    SideAddr<P> d;
+    int c;
+    for (long ti = blockIdx.x; ti < nt; ti += G) {
+        wk.refresh();
+        wk.load(a, ti, v, d, c);
+        wk.process(a, v, d, c, lds);
     }
 }
 

@@ -1,0 +1,14 @@
+// k_c2c_f32.cpp -- complex64 stage kernel configuration and routing.
+#include "k_c2c_impl.hpp"
+
+namespace pfft {
+
+int c2c_config_f32(int N, int contig, int variant, KernelConfig *cfg) { return c2c_config_t<float>(N, contig, variant, cfg); }
+
+hipError_t c2c_launch_f32(int N, int contig, int sign, const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    if (contig) return sign < 0 ? c2c_f32_c_fwd(N, c, a, s) : c2c_f32_c_bwd(N, c, a, s);
+    return sign < 0 ? c2c_f32_s_fwd(N, c, a, s) : c2c_f32_s_bwd(N, c, a, s);
+}
+
+}  // namespace pfft

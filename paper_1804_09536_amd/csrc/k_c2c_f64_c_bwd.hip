@@ -1,0 +1,11 @@
+// k_c2c_f64_c_bwd.hip -- complex128 stage kernels, contiguous tiles, sign 1.
+#include "k_c2c_impl.hpp"
+
+namespace pfft {
+
+hipError_t c2c_f64_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    return c2c_launch_ms<double, true, 1>(N, c, a, s);
+}
+
+}  // namespace pfft

@@ -1,0 +1,11 @@
+// k_c2c_f64_s_bwd.hip -- complex128 stage kernels, strided tiles, sign 1.
+#include "k_c2c_impl.hpp"
+
+namespace pfft {
+
+hipError_t c2c_f64_s_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    return c2c_launch_ms<double, false, 1>(N, c, a, s);
+}
+
+}  // namespace pfft

@@ -1,4 +1,5 @@
-// k_c2c_impl.hpp -- host dispatch over the instantiated lengths of k_c2c.
+// k_c2c_impl.hpp -- host dispatch over the instantiated lengths and tile
+// shapes of k_c2c.
 #pragma once
 
 #include "k_c2c.hpp"
@@ -6,29 +7,98 @@
 
 namespace pfft {
 
-template <typename T, int N, bool CONTIG>
-static hipError_t c2c_launch_n(int sign, const StageArgs &a, hipStream_t s)
+// Number of workgroups of `kernel` (nt threads, static LDS only) that can be
+// resident on the whole device at once.
+int resident_workgroups(const void *kernel, int nt);
+
+// Tile-shape variants: 0 the default, 1 half the lines per tile (more
+// workgroups per CU), 2 twice the lines (wider rows, one workgroup per CU),
+// 3 twice the lines exchanged through the default LDS in two portions (wider
+// rows, two workgroups per CU).
+template <typename T, int N, bool CONTIG, int V>
+struct C2CVariant {
+    using D = C2CDefault<T, N, CONTIG>;
+    static constexpr int VEC = D::VEC;
+    static constexpr int LDS_BYTES_2W = (CONTIG ? 2 * D::W * (N + N / 8) : N * (2 * D::W + 16 / (2 * (int)sizeof(T)))) *
+                                        2 * (int)sizeof(T);
+    static constexpr bool multi = fft_npasses(N) > 1 && N >= 32;
+    static constexpr bool has_half = multi && D::W / 2 >= VEC;
+    static constexpr bool has_double = multi && LDS_BYTES_2W <= 150 * 1024;
+    static constexpr bool has_split = multi && D::W * 2 <= 128 && (2 * D::NL / 2) % VEC == 0;
+    static constexpr int W = V == 1 && has_half ? D::W / 2 : ((V == 2 && has_double) || (V == 3 && has_split) ? 2 * D::W : D::W);
+    static constexpr int NL0 = (V == 2 && has_double) || (V == 3 && has_split) ? 2 * D::NL : D::NL;
+    static constexpr int NL = (W % NL0 == 0) ? NL0 : VEC;
+    static constexpr int H = V == 3 && has_split ? 2 : 1;
+    using type = C2CCfg<T, N, CONTIG, W, NL, H>;
+    static constexpr bool exists = V == 0 || (V == 1 && has_half) || (V == 2 && has_double) || (V == 3 && has_split);
+};
+
+template <typename T, int N, bool CONTIG, int SIGN, int V>
+static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
-    using S = C2CShape<T, N, CONTIG>;
-    dim3 grid((unsigned)a.ntiles), block(S::NT);
-    if (sign < 0)
-        hipLaunchKernelGGL((k_c2c<T, N, CONTIG, -1>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_c2c<T, N, CONTIG, 1>), grid, block, 0, s, a);
+    using S = typename C2CVariant<T, N, CONTIG, V>::type;
+    const void *fn = (const void *)&k_c2c<T, N, CONTIG, SIGN, S>;
+    long g = a.ntiles;
+    if (c.resident) {
+        static const int resident = resident_workgroups(fn, S::NT);
+        if (g > resident) g = resident;
+    }
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int N>
-static void c2c_cfg_n(int contig, KernelConfig *c)
+template <typename T, int N, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
-    if (contig) {
-        c->W = C2CShape<T, N, true>::W;
-        c->threads = C2CShape<T, N, true>::NT;
-    } else {
-        c->W = C2CShape<T, N, false>::W;
-        c->threads = C2CShape<T, N, false>::NT;
+    switch (c.id) {
+    case 1:
+        if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
+        break;
+    case 2:
+        if constexpr (C2CVariant<T, N, CONTIG, 2>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 2>(c, a, s);
+        break;
+    case 3:
+        if constexpr (C2CVariant<T, N, CONTIG, 3>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 3>(c, a, s);
+        break;
+    default: break;
     }
-    c->id = 0;
+    return c2c_launch_v<T, N, CONTIG, SIGN, 0>(c, a, s);
+}
+
+template <typename T, int N, bool CONTIG>
+static void c2c_cfg_mode(int variant, KernelConfig *c)
+{
+    int W, NT, id;
+    if (variant == 1 && C2CVariant<T, N, CONTIG, 1>::exists) {
+        W = C2CVariant<T, N, CONTIG, 1>::type::W;
+        NT = C2CVariant<T, N, CONTIG, 1>::type::NT;
+        id = 1;
+    } else if (variant == 2 && C2CVariant<T, N, CONTIG, 2>::exists) {
+        W = C2CVariant<T, N, CONTIG, 2>::type::W;
+        NT = C2CVariant<T, N, CONTIG, 2>::type::NT;
+        id = 2;
+    } else if (variant == 3 && C2CVariant<T, N, CONTIG, 3>::exists) {
+        W = C2CVariant<T, N, CONTIG, 3>::type::W;
+        NT = C2CVariant<T, N, CONTIG, 3>::type::NT;
+        id = 3;
+    } else {
+        W = C2CVariant<T, N, CONTIG, 0>::type::W;
+        NT = C2CVariant<T, N, CONTIG, 0>::type::NT;
+        id = 0;
+    }
+    c->W = W;
+    c->threads = NT;
+    c->id = id;
+}
+
+template <typename T, int N>
+static void c2c_cfg_n(int contig, int variant, KernelConfig *c)
+{
+    if (contig)
+        c2c_cfg_mode<T, N, true>(variant, c);
+    else
+        c2c_cfg_mode<T, N, false>(variant, c);
 }
 
 #define PFFT_FOR_EACH_N(X)                                                                          \
@@ -36,12 +106,12 @@ static void c2c_cfg_n(int contig, KernelConfig *c)
         X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
 
 template <typename T>
-static int c2c_config_t(int N, int contig, KernelConfig *cfg)
+static int c2c_config_t(int N, int contig, int variant, KernelConfig *cfg)
 {
     switch (N) {
-#define PFFT_CASE(n)              \
-    case n:                       \
-        c2c_cfg_n<T, n>(contig, cfg); \
+#define PFFT_CASE(n)                           \
+    case n:                                    \
+        c2c_cfg_n<T, n>(contig, variant, cfg); \
         return 0;
         PFFT_FOR_EACH_N(PFFT_CASE)
 #undef PFFT_CASE
@@ -50,18 +120,29 @@ static int c2c_config_t(int N, int contig, KernelConfig *cfg)
     }
 }
 
-template <typename T>
-static hipError_t c2c_launch_t(int N, int contig, int sign, const StageArgs &a, hipStream_t s)
+// One translation unit per (precision, mode, sign) instantiates the kernels of
+// every length for that combination (keeps parallel builds short).
+template <typename T, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_ms(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
     switch (N) {
-#define PFFT_CASE(n)                                                                   \
-    case n:                                                                            \
-        return contig ? c2c_launch_n<T, n, true>(sign, a, s) : c2c_launch_n<T, n, false>(sign, a, s);
+#define PFFT_CASE(n) \
+    case n:          \
+        return c2c_launch_s<T, n, CONTIG, SIGN>(c, a, s);
         PFFT_FOR_EACH_N(PFFT_CASE)
 #undef PFFT_CASE
     default:
         return hipErrorInvalidValue;
     }
 }
+
+hipError_t c2c_f32_c_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f32_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f32_s_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f32_s_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f64_c_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f64_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f64_s_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_f64_s_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
 
 }  // namespace pfft

@@ -24,11 +24,11 @@ struct RealLds {
 };
 
 template <typename T, int NR, int KIND>
-__global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageArgs a)
+__global__ __launch_bounds__((C2CDefault<T, NR / 2, true>::type::NT)) void k_real(StageArgs a)
 {
     using T2 = typename V2<T>::type;
     constexpr int M = NR / 2;
-    using S = C2CShape<T, M, true>;
+    using S = typename C2CDefault<T, M, true>::type;
     constexpr int P = S::P, TPL = S::TPL, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
     using LT = LdsTile<T2, M, W, true>;
     using RL = RealLds<T2, M>;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageA
 #pragma unroll
             for (int m = 0; m < P; m++)
                 v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
-        fft_passes<T2, M, W, true, -1, NL, 0>(v, wl, jt, lds, tw);
+        fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
         __syncthreads();
 #pragma unroll
         for (int l = 0; l < NL; l++)
@@ -80,7 +80,7 @@ __global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageA
             for (int m = 0; m < P; m++) {
                 const int k = jt + m * TPL;
                 const T2 zk = lds[RL::idx(wl[l], k)];
-                T2 zc = lds[RL::idx(wl[l], (M - k) & (M - 1))];
+                T2 zc = lds[RL::idx(wl[l], k == 0 ? 0 : M - k)];
                 zc.y = -zc.y;
                 const T2 e = c_scale(c_add(zk, zc), (T)0.5);
                 T2 d = c_sub(zk, zc);  // (Z_k - conj Z_{M-k})
@@ -156,7 +156,7 @@ __global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageA
                 v[l][m] = z;
             }
         __syncthreads();
-        fft_passes<T2, M, W, true, 1, NL, 0>(v, wl, jt, lds, tw);
+        fft_passes<T2, M, W, true, 1, NL, 1, 0>(v, wl, jt, lds, tw);
         SideAddr<P> rs;
         rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
         T *__restrict__ out = (T *)a.dst;
@@ -168,7 +168,9 @@ __global__ __launch_bounds__((C2CShape<T, NR / 2, true>::NT)) void k_real(StageA
     }
 }
 
-#define PFFT_FOR_EACH_NR(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#define PFFT_FOR_EACH_NR(X)                                                                             \
+    X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(6) X(12) X(24) X(48) X(96) \
+        X(192) X(384) X(768) X(1536) X(3072) X(6144)
 
 template <typename T>
 static int real_config_t(int NR, KernelConfig *cfg)
@@ -176,8 +178,8 @@ static int real_config_t(int NR, KernelConfig *cfg)
     switch (NR) {
 #define PFFT_CASE(n)                                 \
     case n:                                          \
-        cfg->W = C2CShape<T, n / 2, true>::W;        \
-        cfg->threads = C2CShape<T, n / 2, true>::NT; \
+        cfg->W = C2CDefault<T, n / 2, true>::type::W;        \
+        cfg->threads = C2CDefault<T, n / 2, true>::type::NT; \
         cfg->id = 0;                                 \
         return 0;
         PFFT_FOR_EACH_NR(PFFT_CASE)
@@ -195,9 +197,9 @@ static hipError_t real_launch_t(int NR, int kind, const StageArgs &a, hipStream_
 #define PFFT_CASE(n)                                                                   \
     case n:                                                                            \
         if (kind == KIND_R2C)                                                          \
-            hipLaunchKernelGGL((k_real<T, n, KIND_R2C>), grid, dim3(C2CShape<T, n / 2, true>::NT), 0, s, a); \
+            hipLaunchKernelGGL((k_real<T, n, KIND_R2C>), grid, dim3(C2CDefault<T, n / 2, true>::type::NT), 0, s, a); \
         else                                                                           \
-            hipLaunchKernelGGL((k_real<T, n, KIND_C2R>), grid, dim3(C2CShape<T, n / 2, true>::NT), 0, s, a); \
+            hipLaunchKernelGGL((k_real<T, n, KIND_C2R>), grid, dim3(C2CDefault<T, n / 2, true>::type::NT), 0, s, a); \
         return hipGetLastError();
         PFFT_FOR_EACH_NR(PFFT_CASE)
 #undef PFFT_CASE

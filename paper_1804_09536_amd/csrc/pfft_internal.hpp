@@ -24,7 +24,7 @@ constexpr int kMaxDims = 8;
 struct Tile {
     int32_t rank[2];
     int32_t count;
-    int32_t pad_;
+    int32_t flags;  // bit 0: every line pair (2i, 2i+1) starts at an even element on both sides
     int64_t O[2];
     int64_t E[2];
     int64_t I[2];
@@ -36,7 +36,8 @@ struct Side {
     const int2 *pos;          // per position along the axis: (block, local index)
     const int32_t *na;        // per block along the axis: local extent
     int32_t R;                // rank stride of the direction splitting the axis
-    int32_t pad_;
+    int32_t un;               // uniform layouts: local extent of the axis in every block
+    int64_t ublock;           // uniform layouts (all blocks equal): block size, else 0
 };
 
 // Kind of a stage kernel.

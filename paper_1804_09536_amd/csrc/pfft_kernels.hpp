@@ -14,13 +14,14 @@ namespace pfft {
 struct KernelConfig {
     int W = 0;
     int threads = 0;
-    int id = 0;
+    int id = 0;        // tile-shape variant: 0 default, 1 half the lines per tile, 2 double
+    int resident = 0;  // 1: grid = resident workgroups looping over tiles; 0: one tile per workgroup
 };
 
 // Fills cfg for a stage kernel (kind: StageKind; prec: 0 = f32, 1 = f64;
 // N: line length; contig: transform axis is the last axis).  Returns 0, or
 // -1 if there is no kernel for this combination.
-int kernel_config(int kind, int prec, int N, int contig, KernelConfig *cfg);
+int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConfig *cfg);
 
 // Enqueue one stage on `stream`.  esize: element bytes for KIND_COPY.
 // Returns a hipError_t value (0 on success).
@@ -28,8 +29,8 @@ int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelCo
                  const StageArgs &args, hipStream_t stream);
 
 // Per-precision tables (defined in the c2c kernel files).
-int c2c_config_f32(int N, int contig, KernelConfig *cfg);
-int c2c_config_f64(int N, int contig, KernelConfig *cfg);
+int c2c_config_f32(int N, int contig, int variant, KernelConfig *cfg);
+int c2c_config_f64(int N, int contig, int variant, KernelConfig *cfg);
 hipError_t c2c_launch_f32(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 hipError_t c2c_launch_f64(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int copy_config(int N, KernelConfig *cfg);

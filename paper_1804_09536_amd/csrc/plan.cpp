@@ -95,7 +95,11 @@ struct Layout {
             int64_t ls[kMaxDims], st[kMaxDims];
             rank_off[r + 1] = rank_off[r] + block(r, ls, st);
         }
+        uniform = true;
+        for (int m = 0; m < nd; m++)
+            if (axis_dir[m] >= 0 && shape[m] % grid[axis_dir[m]] != 0) uniform = false;
     }
+    bool uniform = false;  // every axis split evenly: all blocks have one shape
 
     void coords(int64_t r, int64_t *c) const
     {
@@ -172,6 +176,9 @@ struct pfft_plan_s {
     std::vector<uint8_t> blob;
     std::map<std::pair<int, int>, std::array<size_t, 3>> side_cache;
     std::map<int, std::pair<size_t, size_t>> tw_cache;
+    pfft_tuning tuning{};  // performance knobs (kernel tile variants, grid policy)
+    std::vector<int> chain_in;  // creation arguments kept for rebuilding
+    bool has_chain = false;
     void *dev = nullptr;
     size_t spec_bytes = 0;
     size_t elem = 8;  // complex element bytes
@@ -352,6 +359,22 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W)
             k++;
         }
         t.count = cnt;
+        // flag bit 0: line 0 of the tile sits at an even element at every
+        // position on both sides (so fp32 line pairs move as 16-byte units)
+        bool even = !contig;
+        for (int s = 0; s < 2 && even; s++) {
+            const Layout &L = *S[s];
+            const int64_t npos = L.shape[a];
+            const int d = L.axis_dir[a];
+            const int64_t R = d < 0 ? 0 : L.rstride[d];
+            for (int64_t j = 0; j < npos && even; j++) {
+                const int64_t c = L.own[a][j], loc = L.loc[a][j];
+                const int64_t na = L.local_extent(a, c);
+                const int64_t addr = L.rank_off[t.rank[s] + c * R] + (t.O[s] * na + loc) * t.E[s] + t.I[s];
+                if (addr & 1) even = false;
+            }
+        }
+        t.flags = even ? 1 : 0;
         tiles.push_back(t);
         i = k;
     }
@@ -372,7 +395,10 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     const int prec = p->precision;
     if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
         return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
-    int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, &ln.cfg);
+    const pfft_tuning &tu = p->tuning;
+    const int variant = ln.kind == KIND_C2C ? (ln.contig ? tu.tile_contig : tu.tile_strided) : 0;
+    int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
+    if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0)
         return fail(PFFT_EUNSUPPORTED, "no kernel for length " + std::to_string(ln.N) +
                                            (ln.contig ? " (contiguous)" : " (strided)"));
@@ -544,10 +570,14 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     const int K = (int)p->sched.size();
     // forward: stage k reads where stage k-1 wrote; the last writes the last layout
     std::vector<std::array<int, 5>> fsteps, bsteps;
+    // placement of intermediates: in the layout of the stage that made them
+    // (the next stage gathers) or in the layout of the stage that uses them
+    // (this stage scatters)
+    const bool scatter = (p->flags & PFFT_PLACE_SCATTER) != 0;
     int where = (p->kind == PFFT_R2C) ? p->real0 : 0;
     for (int k = 0; k < K; k++) {
         int li = p->sched[k].first, axis = p->sched[k].second;
-        int dst = (k == K - 1) ? last : li;
+        int dst = (k == K - 1) ? last : (scatter ? p->sched[k + 1].first : li);
         int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : KIND_C2C;
         fsteps.push_back({where, li, dst, axis, kind});
         where = dst;
@@ -555,7 +585,7 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     where = last;
     for (int k = 0; k < K; k++) {
         int li = p->sched[K - 1 - k].first, axis = p->sched[K - 1 - k].second;
-        int dst = (k == K - 1) ? 0 : li;
+        int dst = (k == K - 1) ? 0 : (scatter ? p->sched[K - 2 - k].first : li);
         int kind = KIND_C2C;
         if (k == K - 1 && p->kind == PFFT_R2C) {
             kind = KIND_C2R;
@@ -583,6 +613,19 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
         p->down.push_back(d);
     }
     return PFFT_OK;
+}
+
+// Defaults from measurements of the 512^3 and 256^3 pencil workloads on
+// MI355X: contiguous stages run one tile per workgroup, strided stages a
+// resident grid looping over tiles.
+static pfft_tuning default_tuning()
+{
+    pfft_tuning t;
+    t.tile_contig = 0;
+    t.tile_strided = 0;
+    t.resident_contig = 0;
+    t.resident_strided = 1;
+    return t;
 }
 
 static double axis_scale(const pfft_plan_s *p, int axis, bool forward_factors)
@@ -635,6 +678,12 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
         a.side[s].pos = (const int2 *)(dev + ln.off_pos[s]);
         a.side[s].na = (const int32_t *)(dev + ln.off_na[s]);
         a.side[s].R = ln.R[s];
+        const Layout &L = p->layouts[s == 0 ? ln.src : ln.dst];
+        if (L.uniform) {
+            a.side[s].ublock = L.total() / L.P;
+            int d = L.axis_dir[ln.axis];
+            a.side[s].un = (int32_t)(d < 0 ? L.shape[ln.axis] : L.shape[ln.axis] / L.grid[d]);
+        }
     }
     a.tiles = (const Tile *)(dev + ln.off_tiles);
     a.twiddle = dev + ln.off_tw;
@@ -771,7 +820,7 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
     if (kind != PFFT_C2C && kind != PFFT_R2C) return fail(PFFT_EDTYPE, "bad kind");
     if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
-    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY)) != 0 || (flags & PFFT_PATH_MASK) == 3u)
+    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_SCATTER)) != 0 || (flags & PFFT_PATH_MASK) == 3u)
         return fail(PFFT_EINVAL, "bad flags");
     if (chain && nsteps < 0) return fail(PFFT_EINVAL, "bad nsteps");
     int64_t total = 1;
@@ -786,6 +835,11 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     p->kind = kind;
     p->norm = norm;
     p->flags = flags;
+    p->tuning = default_tuning();
+    if (chain) {
+        p->has_chain = true;
+        p->chain_in.assign(chain, chain + 2 * nsteps);
+    }
     int rc = build_plan(p, chain, chain ? nsteps : 0);
     if (rc != PFFT_OK) {
         delete p;
@@ -794,6 +848,39 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     *out = p;
     return PFFT_OK;
     PFFT_GUARD_END
+}
+
+int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
+{
+    PFFT_GUARD_BEGIN
+    if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
+    if (t->tile_contig < 0 || t->tile_contig > 3 || t->tile_strided < 0 || t->tile_strided > 3 ||
+        t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1)
+        return fail(PFFT_EINVAL, "tuning field out of range");
+    // rebuild every table with the new kernel shapes; the device state must be bound again
+    plan->tuning = *t;
+    plan->dirs.clear();
+    plan->layouts.clear();
+    plan->sched.clear();
+    plan->fwd.clear();
+    plan->bwd.clear();
+    plan->up.clear();
+    plan->down.clear();
+    plan->blob.clear();
+    plan->side_cache.clear();
+    plan->tw_cache.clear();
+    plan->real0 = -1;
+    plan->dev = nullptr;
+    const int n = (int)plan->chain_in.size() / 2;
+    return build_plan(plan, plan->has_chain ? plan->chain_in.data() : nullptr, n);
+    PFFT_GUARD_END
+}
+
+int pfft_plan_get_tuning(pfft_plan plan, pfft_tuning *t)
+{
+    if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
+    *t = plan->tuning;
+    return PFFT_OK;
 }
 
 int pfft_plan_destroy(pfft_plan plan)

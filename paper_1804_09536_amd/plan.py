@@ -42,11 +42,14 @@ class Plan:
           (local transpose + contiguous exchange + realign).
     layouts_only: plan layouts and redistributions only (any lengths); the
           transforms then raise.
+    placement: "gather" (each partial transform's result stays in its own
+          layout; the next one gathers) or "scatter" (written straight into
+          the next one's layout).  Same results; different access patterns.
     """
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
                  norm: str = "forward", chain=None, path: str = "fused", device=None,
-                 layouts_only: bool = False):
+                 layouts_only: bool = False, placement: str = "gather"):
         lib = _lib.load()
         self.shape = tuple(int(x) for x in shape)
         self.grid = tuple(int(x) for x in grid)
@@ -64,7 +67,8 @@ class Plan:
             ch, nsteps = (ctypes.c_int * max(1, len(flat)))(*flat), len(self.chain)
         st = lib.pfft_plan_create(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd,
                                   0 if precision == "f32" else 1, 0 if kind == "c2c" else 1, NORMS[norm],
-                                  ch, nsteps, PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0))
+                                  ch, nsteps, PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0)
+                                  | (_lib.PFFT_PLACE_SCATTER if placement == "scatter" else 0))
         check(st, "pfft_plan_create")
         self._h = h
         n = ctypes.c_int()
@@ -110,6 +114,21 @@ class Plan:
     def validate(self):
         """Host emulation of every kernel's addressing (bounds, write-once)."""
         check(_lib.load().pfft_validate_plan(self._h), "pfft_validate_plan")
+        return self
+
+    def tuning(self) -> dict:
+        t = _lib.Tuning()
+        check(_lib.load().pfft_plan_get_tuning(self._h, ctypes.byref(t)), "pfft_plan_get_tuning")
+        return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
+
+    def set_tuning(self, **knobs):
+        """Change kernel tile shapes / grid policy (see pfft_tuning); results
+        do not change.  Drops the bound device state (rebound on next use)."""
+        cur = self.tuning()
+        cur.update(knobs)
+        t = _lib.Tuning(**cur)
+        check(_lib.load().pfft_plan_set_tuning(self._h, ctypes.byref(t)), "pfft_plan_set_tuning")
+        self._state = None
         return self
 
     def set_profiling(self, enable: bool = True):

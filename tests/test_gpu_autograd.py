@@ -1,0 +1,78 @@
+"""Automatic differentiation through the distributed transforms: gradcheck in
+FP64 on tiny shapes, exact central differences of the quadratic loss, and the
+oracle's gradient on the 256^3 real-input pencil workload."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_09536_amd import autograd as pad
+from paper_1804_09536_amd import inputs
+from paper_1804_09536_amd.plan import Plan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind", ["c2c", "r2c"])
+def test_gradcheck_tiny(kind):
+    p = Plan((4, 8, 6), (2, 2), precision="f64", kind=kind) if kind == "c2c" else \
+        Plan((4, 8, 8), (2, 2), precision="f64", kind=kind)
+    n = p.buffer_numel(0, real=(kind == "r2c"))
+    dt = torch.complex128 if kind == "c2c" else torch.float64
+    x = torch.randn(n, dtype=dt, device="cuda", generator=torch.Generator("cuda").manual_seed(0)).requires_grad_()
+    assert torch.autograd.gradcheck(lambda t: pad.forward(t, p), (x,), eps=1e-6, atol=1e-8)
+    z = torch.randn(p.buffer_numel(p.num_layouts - 1), dtype=torch.complex128, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(1)).requires_grad_()
+    assert torch.autograd.gradcheck(lambda t: pad.backward(t, p), (z,), eps=1e-6, atol=1e-8)
+
+
+def test_weight_matches_oracle():
+    shape, grid = (16, 12, 16), (4, 3)
+    p = Plan(shape, grid, precision="f64", kind="r2c")
+    ch = oracle.Chain.paper(shape, grid, kind="r2c")
+    w = pad.wavenumber_weight(p).cpu().numpy()
+    wg = oracle.wavenumber_weight(ch.spectral_shape(), real_last=True)
+    expect = np.real(oracle.scatter_global(wg.astype(np.complex128), ch.output_layout()))
+    assert np.array_equal(w, expect)
+
+
+def _loss(p, u, w):
+    uh = pad.forward(u, p)
+    return torch.sum(w * (uh.real ** 2 + uh.imag ** 2))
+
+
+def test_exact_central_differences_16cubed():
+    # the loss is quadratic, so central differences are exact for any step
+    p = Plan((16, 16, 16), (4, 4), precision="f64", kind="r2c")
+    w = pad.wavenumber_weight(p)
+    u0 = inputs.gaussian_real(p.buffer_numel(0, real=True), [24], np.float64)
+    u = torch.from_numpy(u0).cuda().requires_grad_()
+    loss = _loss(p, u, w)
+    loss.backward()
+    g = u.grad.cpu().numpy()
+    rng = np.random.default_rng(7)
+    for i in rng.choice(u0.size, size=24, replace=False):
+        e = torch.zeros_like(u)
+        e[i] = 1.0
+        with torch.no_grad():
+            lp = float(_loss(p, u + e, w))
+            lm = float(_loss(p, u - e, w))
+        fd = (lp - lm) / 2.0
+        assert abs(fd - g[i]) <= 1e-9 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_gradient_256cubed_matches_oracle():
+    shape, grid = (256, 256, 256), (4, 4)
+    print("case", shape, grid, flush=True)
+    p = Plan(shape, grid, kind="r2c")
+    ch = oracle.Chain.paper(shape, grid, kind="r2c")
+    w = pad.wavenumber_weight(p)
+    u0 = inputs.gaussian_real(p.buffer_numel(0, real=True), [5], np.float32)
+    u = torch.from_numpy(u0).cuda().requires_grad_()
+    loss = _loss(p, u, w.to(torch.float32))
+    loss.backward()
+    g = u.grad.cpu().numpy()
+    wg = w.cpu().numpy()
+    eloss, egrad = oracle.loss_and_grad(ch, u0.astype(np.float64), wg)
+    assert abs(float(loss) - eloss) <= 1e-5 * abs(eloss)
+    assert np.linalg.norm(g - egrad) / np.linalg.norm(egrad) <= 1e-5

@@ -116,3 +116,25 @@ def test_other_normalisations(norm):
     back = oracle.backward(ch, oracle.forward(ch, u0))
     scale = 1.0 if norm == "backward" else float(n)
     assert np.allclose(back, scale * u0, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 5), (3, 5, 7, 2), (8, 1, 6)])
+def test_dft_bins_equal_bruteforce(shape):
+    n = int(np.prod(shape))
+    G = inputs.uniform_complex(n, [15, n], np.complex128).reshape(shape)
+    full = oracle.bruteforce_dftn(G, -1, 1.0 / n)
+    rng = np.random.default_rng(3)
+    bins = [tuple(int(rng.integers(0, s)) for s in shape) for _ in range(6)]
+    got = oracle.dft_bins(G, bins, -1, 1.0 / n)
+    assert np.allclose(got, [full[b] for b in bins], rtol=0, atol=1e-14)
+
+
+def test_layout_offset_matches_scatter():
+    shape, grid = (5, 7, 6), (2, 3)
+    ch = oracle.Chain.paper(shape, grid)
+    G = np.arange(np.prod(shape)).reshape(shape).astype(np.complex128)
+    for li in range(len(ch.dirs)):
+        lay = ch.layout(li)
+        buf = oracle.scatter_global(G, lay)
+        for g in [(0, 0, 0), (4, 6, 5), (2, 3, 1), (1, 5, 4)]:
+            assert buf[oracle.layout_offset(lay, g)] == G[g]
