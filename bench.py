@@ -46,7 +46,29 @@ def parse():
     ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
+    ap.add_argument("--placement", default="gather", choices=["gather", "scatter"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy one buffer of the workload's size with torch (a "
+                         "known-size reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pencil512_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("kernel_sources", []):
+        with open(os.path.join(ROOT, "paper_1804_09536_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    return rec.get("traffic_bytes_per_launch", {}).get(kernel)
 
 
 def kernel_name(rec):
@@ -87,7 +109,8 @@ def main():
     shape, grid, kind, prec, chain = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev).bind()
+    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev,
+                placement=args.placement).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
     if kind == "c2c":
         u_np = inputs.uniform_complex(n_in, [4], np.complex64 if prec == "f32" else np.complex128)
@@ -136,12 +159,20 @@ def main():
         avg_ms = d["ms"] / d["n"]
         per_launch = d["bytes"] / d["n"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(dom) if (args.workload == "pencil512" and args.placement == "gather"
+                                            and args.path == "fused") else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": 8000.0,
-                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": per_launch}
     # round-trip sanity on the last step
-    zz = z.float() if kind == "c2c" else z
-    rt = float(torch.linalg.vector_norm((zz - x.to(zz.dtype)).flatten()) / torch.linalg.vector_norm(x.flatten()))
+    rt = float(torch.linalg.vector_norm((z - x).flatten()) / torch.linalg.vector_norm(x.flatten()))
+
+    if args.copy_calibration:
+        ref = torch.empty_like(y)
+        for _ in range(3):
+            ref.copy_(y)
+        torch.cuda.synchronize()
+        del ref
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -163,7 +194,8 @@ def main():
         "config": {"workload": "%s %s %s on a %s virtual-rank grid, forward+backward, %s path"
                                % ("x".join(map(str, shape)), kind, "complex64" if prec == "f32" else "complex128",
                                   "x".join(map(str, grid)), args.path),
-                   "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path},
+                   "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path,
+                   "placement": args.placement, "tuning": plan.tuning()},
         "step_bytes": step_bytes,
         "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
         "roundtrip_rel_l2": rt,

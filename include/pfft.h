@@ -197,6 +197,35 @@ int pfft_adjoint_forward(pfft_plan plan, const void *in, void *out, void *work, 
 int pfft_adjoint_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
 
 /*
+ * Batches: many plans (any shapes and grids, one precision) executed
+ * together.  Launch k of every member that runs the same stage kernel shape
+ * becomes one launch over all their tiles, so a batch of n transforms costs
+ * about as many kernel launches as one transform of each distinct shape;
+ * execution is asynchronous, allocates nothing and can be captured into a
+ * HIP graph.  The batch copies what it needs from its plans at creation
+ * (member plans may be changed or destroyed afterwards).
+ *
+ * Buffers: one input, one output and one workspace buffer for the whole
+ * batch, each holding every member's region at the offsets
+ * pfft_batch_member_offsets returns (256-byte aligned); a member's input
+ * region is its layout 0, its output region its last layout.  Direction 0
+ * runs every member's forward transform (input -> output), direction 1 every
+ * backward transform (output -> input, overwriting the input region).
+ */
+typedef struct pfft_batch_s *pfft_batch;
+
+int pfft_batch_create(pfft_batch *out, int nplans, const pfft_plan *plans);
+int pfft_batch_destroy(pfft_batch batch);
+int pfft_batch_buffer_bytes(pfft_batch batch, size_t *in_bytes, size_t *out_bytes, size_t *work_bytes);
+int pfft_batch_member_offsets(pfft_batch batch, int member, size_t *in_offset, size_t *out_offset);
+int pfft_batch_device_state_bytes(pfft_batch batch, size_t *bytes);
+/* Upload tables and kernel arguments for these buffers (device pointers, the
+ * state 256-byte aligned); waits for the upload.  Bind again to use other
+ * buffers. */
+int pfft_batch_bind(pfft_batch batch, void *state, void *in, void *out, void *work, hipStream_t stream);
+int pfft_batch_execute(pfft_batch batch, int direction, hipStream_t stream);
+
+/*
  * Host-side self-check of a plan (no device needed): emulates the address
  * arithmetic of every kernel launch the plan can make and verifies that each
  * access stays inside its rank block and buffer and that every destination

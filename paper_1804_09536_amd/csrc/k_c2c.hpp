@@ -97,10 +97,9 @@ struct C2CWorker {
     // Compute both sides' addresses of tile `ti` and issue its loads.  A full
     // tile whose addresses are even on both sides (Tile flag bit 0) takes the
     // unpredicated path; others are predicated line by line.
-    __device__ __forceinline__ void load(const StageArgs &a, long ti, T2 (&v)[NL][P], SideAddr<P> &dst,
+    __device__ __forceinline__ void load(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], SideAddr<P> &dst,
                                          int &count) const
     {
-        const Tile &t = a.tiles[ti];
         count = t.count;
         const bool fast = (t.count == W) && (VEC == 1 || (t.flags & 1));
         if (!fast) count = -count;  // sign marks the predicated path for process()
@@ -201,7 +200,32 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     int c;
     for (long ti = blockIdx.x; ti < nt; ti += G) {
         wk.refresh();
-        wk.load(a, ti, v, d, c);
+        wk.load(a, a.tiles[ti], v, d, c);
+        wk.process(a, v, d, c, lds);
+    }
+}
+
+// The same stage for tiles of several transforms in one launch: each tile
+// carries the index of its transform's arguments in bits 8..31 of its flags.
+template <typename T, int N, bool CONTIG, int SIGN, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c_multi(
+    const StageArgs *__restrict__ args, const Tile *__restrict__ tiles, long nt)
+{
+    using Wk = C2CWorker<T, N, CONTIG, SIGN, S>;
+    using T2 = typename Wk::T2;
+    constexpr int NL = S::NL, P = S::P;
+    __shared__ T2 lds[Wk::LDS_SIZE];
+    Wk wk;
+    wk.init_geometry();
+    const long G = gridDim.x;
+    T2 v[NL][P];
+    SideAddr<P> d;
+    int c;
+    for (long ti = blockIdx.x; ti < nt; ti += G) {
+        const Tile &t = tiles[ti];
+        const StageArgs &a = args[(unsigned)t.flags >> 8];
+        wk.refresh();
+        wk.load(a, t, v, d, c);
         wk.process(a, v, d, c, lds);
     }
 }

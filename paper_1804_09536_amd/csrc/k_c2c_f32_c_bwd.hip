@@ -8,4 +8,10 @@ hipError_t c2c_f32_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipSt
     return c2c_launch_ms<float, true, 1>(N, c, a, s);
 }
 
+hipError_t c2c_multi_f32_c_bwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s)
+{
+    return c2c_launch_multi_ms<float, true, 1>(N, c, args, tiles, nt, s);
+}
+
 }  // namespace pfft

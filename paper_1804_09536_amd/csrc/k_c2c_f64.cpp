@@ -11,4 +11,11 @@ hipError_t c2c_launch_f64(int N, int contig, int sign, const KernelConfig &c, co
     return sign < 0 ? c2c_f64_s_fwd(N, c, a, s) : c2c_f64_s_bwd(N, c, a, s);
 }
 
+hipError_t c2c_launch_multi_f64(int N, int contig, int sign, const KernelConfig &c, const StageArgs *args,
+                                const Tile *tiles, long nt, hipStream_t s)
+{
+    if (contig) return sign < 0 ? c2c_multi_f64_c_fwd(N, c, args, tiles, nt, s) : c2c_multi_f64_c_bwd(N, c, args, tiles, nt, s);
+    return sign < 0 ? c2c_multi_f64_s_fwd(N, c, args, tiles, nt, s) : c2c_multi_f64_s_bwd(N, c, args, tiles, nt, s);
+}
+
 }  // namespace pfft

@@ -48,6 +48,44 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
     return hipGetLastError();
 }
 
+template <typename T, int N, bool CONTIG, int SIGN, int V>
+static hipError_t c2c_launch_multi_v(const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                                     hipStream_t s)
+{
+    using S = typename C2CVariant<T, N, CONTIG, V>::type;
+    const void *fn = (const void *)&k_c2c_multi<T, N, CONTIG, SIGN, S>;
+    long g = nt;
+    if (c.resident) {
+        static const int resident = resident_workgroups(fn, S::NT);
+        if (g > resident) g = resident;
+    }
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((k_c2c_multi<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, args, tiles, nt);
+    return hipGetLastError();
+}
+
+template <typename T, int N, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_multi_s(const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                                     hipStream_t s)
+{
+    switch (c.id) {
+    case 1:
+        if constexpr (C2CVariant<T, N, CONTIG, 1>::exists)
+            return c2c_launch_multi_v<T, N, CONTIG, SIGN, 1>(c, args, tiles, nt, s);
+        break;
+    case 2:
+        if constexpr (C2CVariant<T, N, CONTIG, 2>::exists)
+            return c2c_launch_multi_v<T, N, CONTIG, SIGN, 2>(c, args, tiles, nt, s);
+        break;
+    case 3:
+        if constexpr (C2CVariant<T, N, CONTIG, 3>::exists)
+            return c2c_launch_multi_v<T, N, CONTIG, SIGN, 3>(c, args, tiles, nt, s);
+        break;
+    default: break;
+    }
+    return c2c_launch_multi_v<T, N, CONTIG, SIGN, 0>(c, args, tiles, nt, s);
+}
+
 template <typename T, int N, bool CONTIG, int SIGN>
 static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
@@ -136,13 +174,44 @@ static hipError_t c2c_launch_ms(int N, const KernelConfig &c, const StageArgs &a
     }
 }
 
+template <typename T, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_multi_ms(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                                      hipStream_t s)
+{
+    switch (N) {
+#define PFFT_CASE(n) \
+    case n:          \
+        return c2c_launch_multi_s<T, n, CONTIG, SIGN>(c, args, tiles, nt, s);
+        PFFT_FOR_EACH_N(PFFT_CASE)
+#undef PFFT_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 hipError_t c2c_f32_c_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f32_c_fwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f32_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f32_c_bwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f32_s_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f32_s_fwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f32_s_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f32_s_bwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f64_c_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f64_c_fwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f64_c_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f64_c_bwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f64_s_fwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f64_s_fwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 hipError_t c2c_f64_s_bwd(int N, const KernelConfig &c, const StageArgs &a, hipStream_t s);
+hipError_t c2c_multi_f64_s_bwd(int N, const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
+                              hipStream_t s);
 
 }  // namespace pfft

@@ -33,6 +33,10 @@ int c2c_config_f32(int N, int contig, int variant, KernelConfig *cfg);
 int c2c_config_f64(int N, int contig, int variant, KernelConfig *cfg);
 hipError_t c2c_launch_f32(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 hipError_t c2c_launch_f64(int N, int contig, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+hipError_t c2c_launch_multi_f32(int N, int contig, int sign, const KernelConfig &c, const StageArgs *args,
+                                const Tile *tiles, long nt, hipStream_t s);
+hipError_t c2c_launch_multi_f64(int N, int contig, int sign, const KernelConfig &c, const StageArgs *args,
+                                const Tile *tiles, long nt, hipStream_t s);
 int copy_config(int N, KernelConfig *cfg);
 hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int real_config(int prec, int N, int kind, KernelConfig *cfg);

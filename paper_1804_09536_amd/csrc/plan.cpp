@@ -615,16 +615,17 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     return PFFT_OK;
 }
 
-// Defaults from measurements of the 512^3 and 256^3 pencil workloads on
-// MI355X: contiguous stages run one tile per workgroup, strided stages a
-// resident grid looping over tiles.
+// Defaults from a sweep of the 512^3 complex64 pencil workload on MI355X:
+// contiguous stages with half-size tiles (four workgroups per CU), strided
+// stages with double-width tiles exchanged in two LDS portions (256-byte rows,
+// two workgroups per CU), one tile per workgroup for both.
 static pfft_tuning default_tuning()
 {
     pfft_tuning t;
-    t.tile_contig = 0;
-    t.tile_strided = 0;
+    t.tile_contig = 1;
+    t.tile_strided = 3;
     t.resident_contig = 0;
-    t.resident_strided = 1;
+    t.resident_strided = 0;
     return t;
 }
 
@@ -657,18 +658,10 @@ static double launch_bytes(const pfft_plan_s *p, const Launch &ln)
     return (double)p->layouts[ln.src].total() * esz(ln.src) + (double)p->layouts[ln.dst].total() * esz(ln.dst);
 }
 
-static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
-                      int flags, hipStream_t stream, int direction = 4)
+// Kernel arguments of one launch, with the plan's tables at device address dev.
+static StageArgs stage_args(const pfft_plan_s *p, const Launch &ln, const uint8_t *dev, const void *src, void *dst,
+                            double scale, int flags)
 {
-    if (ln.ntiles == 0) return PFFT_OK;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    if (p->profiling) {
-        ea = pool_event(p);
-        eb = pool_event(p);
-        if (!ea || !eb) return fail(PFFT_EHIP, "hipEventCreate failed");
-        if (hipEventRecord(ea, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
-    }
-    const uint8_t *dev = (const uint8_t *)p->dev;
     StageArgs a;
     memset(&a, 0, sizeof a);
     a.src = src;
@@ -692,9 +685,28 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
     a.scale = scale;
     a.N = ln.N;
     a.flags = flags;
-    size_t esize = p->elem;
-    if (ln.kind == KIND_COPY && (ln.src == p->real0 || ln.dst == p->real0)) esize = p->elem / 2;
-    int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, esize, a, stream);
+    return a;
+}
+
+static size_t launch_esize(const pfft_plan_s *p, const Launch &ln)
+{
+    if (ln.kind == KIND_COPY && (ln.src == p->real0 || ln.dst == p->real0)) return p->elem / 2;
+    return p->elem;
+}
+
+static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
+                      int flags, hipStream_t stream, int direction = 4)
+{
+    if (ln.ntiles == 0) return PFFT_OK;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (p->profiling) {
+        ea = pool_event(p);
+        eb = pool_event(p);
+        if (!ea || !eb) return fail(PFFT_EHIP, "hipEventCreate failed");
+        if (hipEventRecord(ea, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
+    }
+    const StageArgs a = stage_args(p, ln, (const uint8_t *)p->dev, src, dst, scale, flags);
+    int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
     if (rc != 0) return fail(PFFT_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     if (p->profiling) {
         if (hipEventRecord(eb, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
@@ -705,6 +717,33 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
 
 // Run a launch list with ping-pong buffers so the last launch writes `out`.
 // mode 0: forward factors from norm on forward, 1: backward factors.
+// Source and destination buffer of every launch of a list that reads `in`
+// and must end in `out`, ping-ponging through the workspace.
+static void assign_buffers(const pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out,
+                           void *work, std::vector<const void *> &srcs, std::vector<void *> &dsts)
+{
+    const int n = (int)list.size();
+    uint8_t *w0 = (uint8_t *)work;
+    uint8_t *w1 = w0 ? w0 + ((p->spec_bytes + 255) & ~(size_t)255) : nullptr;
+    const bool out_is_real = n > 0 && list.back().dst == p->real0;
+    const void *cur = in;
+    int parity = 0;
+    srcs.assign(n, nullptr);
+    dsts.assign(n, nullptr);
+    for (int k = 0; k < n; k++) {
+        void *dst;
+        if (k == n - 1)
+            dst = out;
+        else if (out_is_real)
+            dst = (parity++ % 2 == 0) ? (void *)w0 : (void *)w1;
+        else
+            dst = ((n - 1 - k) % 2 == 0) ? out : (void *)w0;
+        srcs[k] = cur;
+        dsts[k] = dst;
+        cur = dst;
+    }
+}
+
 static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out, void *work,
                     bool forward_factors, int sign, int r2c_flags, hipStream_t stream, int direction)
 {
@@ -713,31 +752,20 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
     if (!in || !out) return fail(PFFT_EINVAL, "null buffer");
     const int n = (int)list.size();
     if (n > 1 && !work) return fail(PFFT_EINVAL, "null workspace");
-    uint8_t *w0 = (uint8_t *)work;
-    uint8_t *w1 = w0 ? w0 + ((p->spec_bytes + 255) & ~(size_t)255) : nullptr;
-    const void *cur = in;
-    // does the final launch write a real layout (c2r)? then intermediates can't use out
-    bool out_is_real = (list.back().dst == p->real0);
-    int parity = 0;
+    std::vector<const void *> srcs;
+    std::vector<void *> dsts;
+    assign_buffers(p, list, in, out, work, srcs, dsts);
     for (int k = 0; k < n; k++) {
         const Launch &ln = list[k];
-        void *dst;
-        if (k == n - 1) {
-            dst = out;
-        } else if (out_is_real) {
-            dst = (parity++ % 2 == 0) ? (void *)w0 : (void *)w1;
-        } else {
-            dst = ((n - 1 - k) % 2 == 0) ? out : (void *)w0;
-        }
         double scale = (ln.kind == KIND_COPY) ? 1.0 : axis_scale(p, ln.scale_axis, forward_factors);
         int flags = 0;
         if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) flags = r2c_flags;
-        int rc = run_launch(p, ln, cur, dst, scale, sign, flags, stream, direction);
+        int rc = run_launch(p, ln, srcs[k], dsts[k], scale, sign, flags, stream, direction);
         if (rc) return rc;
-        cur = dst;
     }
     return PFFT_OK;
 }
+
 
 // Host emulation of the address arithmetic every kernel of a launch performs:
 // all reads and writes must stay inside their buffers and every destination
@@ -782,6 +810,149 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
         if (hits[e] != 1) return fail(PFFT_EINTERNAL, std::string(what) + ": destination element written " +
                                                           std::to_string(hits[e]) + " times");
     return PFFT_OK;
+}
+
+
+// ------------------------------------------------------------- batches --
+
+struct BatchGroup {
+    int k = 0;              // launch index within each member's list
+    int kind = KIND_C2C;
+    int N = 0, contig = 0;
+    KernelConfig cfg;
+    std::vector<int> members;  // member plan indices (C2C groups)
+    size_t off_tiles = 0;      // merged tiles in the batch state
+    int64_t ntiles = 0;
+    size_t off_args = 0;       // one StageArgs per member
+};
+
+}  // namespace pfft
+
+struct pfft_batch_s {
+    std::vector<pfft_plan_s *> plans;
+    int precision = 0;
+    std::vector<size_t> in_off, out_off, work_off, blob_off;
+    size_t in_bytes = 0, out_bytes = 0, work_bytes = 0;
+    std::vector<pfft::BatchGroup> groups[2];  // forward, backward; in execution order
+    std::vector<uint8_t> blob;                 // host image of the batch device state
+    void *dev = nullptr, *in = nullptr, *out = nullptr, *work = nullptr;
+};
+
+namespace pfft {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t blob_reserve(std::vector<uint8_t> &b, size_t bytes)
+{
+    size_t off = align256(b.size());
+    b.resize(off + std::max<size_t>(bytes, 1), 0);
+    return off;
+}
+
+// Group the members' launches: launch k of every member with the same kernel
+// shape runs in one multi-transform launch (complex stages); other kinds run
+// per member.  Groups are ordered by k, so every member's launches keep their
+// order.
+static int batch_plan(pfft_batch_s *b)
+{
+    const int nm = (int)b->plans.size();
+    for (int m = 0; m < nm; m++) {
+        pfft_plan_s *p = b->plans[m];
+        b->in_off.push_back(b->in_bytes);
+        b->out_off.push_back(b->out_bytes);
+        b->work_off.push_back(b->work_bytes);
+        size_t ib = (size_t)p->layouts[p->kind == PFFT_R2C ? p->real0 : 0].total() *
+                    (p->kind == PFFT_R2C ? p->elem / 2 : p->elem);
+        size_t ob = (size_t)p->layouts[p->nlayouts - 1].total() * p->elem;
+        // the backward writes the input layout, so both buffers hold either
+        b->in_bytes += align256(std::max(ib, ob));
+        b->out_bytes += align256(std::max(ib, ob));
+        b->work_bytes += align256(p->spec_bytes) * (p->kind == PFFT_R2C ? 2 : 1);
+        b->blob_off.push_back(blob_reserve(b->blob, p->blob.size()));
+        memcpy(b->blob.data() + b->blob_off.back(), p->blob.data(), p->blob.size());
+    }
+    for (int dir = 0; dir < 2; dir++) {
+        size_t maxk = 0;
+        for (auto *p : b->plans) maxk = std::max(maxk, (dir == 0 ? p->fwd : p->bwd).size());
+        for (size_t k = 0; k < maxk; k++) {
+            std::vector<BatchGroup> gs;
+            for (int m = 0; m < nm; m++) {
+                const auto &list = dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd;
+                if (k >= list.size()) continue;
+                const Launch &ln = list[k];
+                BatchGroup *g = nullptr;
+                if (ln.kind == KIND_C2C)
+                    for (auto &x : gs)
+                        if (x.kind == KIND_C2C && x.N == ln.N && x.contig == ln.contig && x.cfg.id == ln.cfg.id &&
+                            x.cfg.resident == ln.cfg.resident)
+                            g = &x;
+                if (!g) {
+                    gs.emplace_back();
+                    g = &gs.back();
+                    g->k = (int)k;
+                    g->kind = ln.kind;
+                    g->N = ln.N;
+                    g->contig = ln.contig;
+                    g->cfg = ln.cfg;
+                }
+                g->members.push_back(m);
+            }
+            for (auto &g : gs) {
+                if (g.kind == KIND_C2C) {
+                    int64_t nt = 0;
+                    for (int m : g.members) nt += (dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd)[k].ntiles;
+                    if ((int64_t)g.members.size() >= (1 << 23)) return fail(PFFT_EINVAL, "too many batch members");
+                    g.ntiles = nt;
+                    g.off_tiles = blob_reserve(b->blob, (size_t)nt * sizeof(Tile));
+                    Tile *dst = (Tile *)(b->blob.data() + g.off_tiles);
+                    for (size_t mi = 0; mi < g.members.size(); mi++) {
+                        const pfft_plan_s *p = b->plans[g.members[mi]];
+                        const Launch &ln = (dir == 0 ? p->fwd : p->bwd)[k];
+                        const Tile *src = (const Tile *)(p->blob.data() + ln.off_tiles);
+                        for (int64_t t = 0; t < ln.ntiles; t++) {
+                            *dst = src[t];
+                            dst->flags = (src[t].flags & 0xff) | (int32_t)(mi << 8);
+                            dst++;
+                        }
+                    }
+                    g.off_args = blob_reserve(b->blob, g.members.size() * sizeof(StageArgs));
+                }
+                b->groups[dir].push_back(g);
+            }
+        }
+    }
+    return PFFT_OK;
+}
+
+// With the batch's buffers known, write every member's kernel arguments.
+static void batch_fill_args(pfft_batch_s *b)
+{
+    const uint8_t *dev = (const uint8_t *)b->dev;
+    for (int dir = 0; dir < 2; dir++) {
+        for (auto &g : b->groups[dir]) {
+            if (g.kind != KIND_C2C) continue;
+            StageArgs *args = (StageArgs *)(b->blob.data() + g.off_args);
+            for (size_t mi = 0; mi < g.members.size(); mi++) {
+                const int m = g.members[mi];
+                const pfft_plan_s *p = b->plans[m];
+                const auto &list = dir == 0 ? p->fwd : p->bwd;
+                std::vector<const void *> srcs;
+                std::vector<void *> dsts;
+                uint8_t *in = (uint8_t *)b->in + b->in_off[m], *out = (uint8_t *)b->out + b->out_off[m];
+                uint8_t *work = (uint8_t *)b->work + b->work_off[m];
+                if (dir == 0)
+                    assign_buffers(p, list, in, out, work, srcs, dsts);
+                else  // the backward reads the forward's output buffer and writes the input buffer
+                    assign_buffers(p, list, out, in, work, srcs, dsts);
+                const Launch &ln = list[g.k];
+                double scale = axis_scale(p, ln.scale_axis, dir == 0);
+                StageArgs a = stage_args(p, ln, dev + b->blob_off[m], srcs[g.k], dsts[g.k], scale, 0);
+                a.tiles = nullptr;
+                a.ntiles = 0;
+                args[mi] = a;
+            }
+        }
+    }
 }
 
 }  // namespace pfft
@@ -1056,6 +1227,132 @@ int pfft_validate_plan(pfft_plan plan)
             int rc = validate_launch(plan, ln, names[li]);
             if (rc) return rc;
         }
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_batch_create(pfft_batch *out, int nplans, const pfft_plan *plans)
+{
+    PFFT_GUARD_BEGIN
+    if (!out || !plans || nplans < 1) return fail(PFFT_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    pfft_batch_s *b = new pfft_batch_s();
+    for (int i = 0; i < nplans; i++) {
+        if (!plans[i]) {
+            delete b;
+            return fail(PFFT_EINVAL, "null plan in batch");
+        }
+        if (plans[i]->flags & PFFT_LAYOUTS_ONLY) {
+            delete b;
+            return fail(PFFT_EUNSUPPORTED, "a layouts-only plan cannot join a batch");
+        }
+        if (i > 0 && plans[i]->precision != plans[0]->precision) {
+            delete b;
+            return fail(PFFT_EDTYPE, "batch members must share one precision");
+        }
+        b->plans.push_back(plans[i]);
+    }
+    b->precision = plans[0]->precision;
+    int rc = batch_plan(b);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_batch_destroy(pfft_batch batch)
+{
+    if (!batch) return fail(PFFT_EINVAL, "null batch");
+    delete batch;
+    return PFFT_OK;
+}
+
+int pfft_batch_buffer_bytes(pfft_batch b, size_t *in_bytes, size_t *out_bytes, size_t *work_bytes)
+{
+    if (!b || !in_bytes || !out_bytes || !work_bytes) return fail(PFFT_EINVAL, "null argument");
+    *in_bytes = std::max<size_t>(b->in_bytes, 256);
+    *out_bytes = std::max<size_t>(b->out_bytes, 256);
+    *work_bytes = std::max<size_t>(b->work_bytes, 256);
+    return PFFT_OK;
+}
+
+int pfft_batch_member_offsets(pfft_batch b, int member, size_t *in_offset, size_t *out_offset)
+{
+    if (!b || !in_offset || !out_offset) return fail(PFFT_EINVAL, "null argument");
+    if (member < 0 || member >= (int)b->plans.size()) return fail(PFFT_EINVAL, "member out of range");
+    *in_offset = b->in_off[member];
+    *out_offset = b->out_off[member];
+    return PFFT_OK;
+}
+
+int pfft_batch_device_state_bytes(pfft_batch b, size_t *bytes)
+{
+    if (!b || !bytes) return fail(PFFT_EINVAL, "null argument");
+    *bytes = align256(b->blob.size());
+    return PFFT_OK;
+}
+
+int pfft_batch_bind(pfft_batch b, void *state, void *in, void *out, void *work, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!b || !state || !in || !out || !work) return fail(PFFT_EINVAL, "null argument");
+    if (((uintptr_t)state & 255u) != 0) return fail(PFFT_EINVAL, "device state must be 256-byte aligned");
+    b->dev = state;
+    b->in = in;
+    b->out = out;
+    b->work = work;
+    batch_fill_args(b);
+    hipError_t e = hipMemcpyAsync(state, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        b->dev = nullptr;
+        return fail(PFFT_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+    }
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    if (!b) return fail(PFFT_EINVAL, "null batch");
+    if (direction != 0 && direction != 1) return fail(PFFT_EINVAL, "direction must be 0 (forward) or 1 (backward)");
+    if (!b->dev) return fail(PFFT_EWORKSPACE, "batch not bound");
+    const uint8_t *dev = (const uint8_t *)b->dev;
+    const int sign = direction == 0 ? -1 : 1;
+    for (const auto &g : b->groups[direction]) {
+        if (g.kind == KIND_C2C) {
+            if (g.ntiles == 0) continue;
+            const StageArgs *args = (const StageArgs *)(dev + g.off_args);
+            const Tile *tiles = (const Tile *)(dev + g.off_tiles);
+            hipError_t e = b->precision == PFFT_F32
+                               ? c2c_launch_multi_f32(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream)
+                               : c2c_launch_multi_f64(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream);
+            if (e != hipSuccess) return fail(PFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+            continue;
+        }
+        for (int m : g.members) {
+            pfft_plan_s *p = b->plans[m];
+            const auto &list = direction == 0 ? p->fwd : p->bwd;
+            const Launch &ln = list[g.k];
+            if (ln.ntiles == 0) continue;
+            std::vector<const void *> srcs;
+            std::vector<void *> dsts;
+            uint8_t *in = (uint8_t *)b->in + b->in_off[m], *out = (uint8_t *)b->out + b->out_off[m];
+            uint8_t *work = (uint8_t *)b->work + b->work_off[m];
+            if (direction == 0)
+                assign_buffers(p, list, in, out, work, srcs, dsts);
+            else
+                assign_buffers(p, list, out, in, work, srcs, dsts);
+            double scale = ln.kind == KIND_COPY ? 1.0 : axis_scale(p, ln.scale_axis, direction == 0);
+            StageArgs a = stage_args(p, ln, dev + b->blob_off[m], srcs[g.k], dsts[g.k], scale, 0);
+            int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
+            if (rc != 0) return fail(PFFT_EHIP, std::string("batch launch: ") + hipGetErrorString((hipError_t)rc));
+        }
+    }
     return PFFT_OK;
     PFFT_GUARD_END
 }
