@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pencil512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pencil512", choices=sorted(WORKLOADS) + ["batch168"])
     ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
@@ -94,6 +94,84 @@ def cpu_baseline(shape, grid, kind, chain, u_np):
             "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)"}
 
 
+BATCH_SHAPES = [
+    # (shape, grid): the mixed workload of many uneven transforms, 8 instances x 3 field components each
+    ((64, 64, 64), (4,)),
+    ((96, 96, 96), (8,)),
+    ((128, 128, 128), (4, 4)),
+    ((192, 192, 192), (4, 4)),
+    ((256, 256, 256), (4, 4)),
+    ((384, 384, 384), (8, 8)),
+    ((128, 256, 512), (4, 8)),
+]
+
+
+def bench_batch(args):
+    """168 complex64 transforms (7 shapes x 8 instances x 3 components): the
+    batch (one launch per stage and kernel shape, captured in a HIP graph)
+    against one call per transform."""
+    import torch
+
+    from paper_1804_09536_amd import inputs
+    from paper_1804_09536_amd.plan import Batch, Plan
+
+    dev = torch.device("cuda:0")
+    uniq = [Plan(s, g, device=dev).bind() for s, g in BATCH_SHAPES]
+    members = [p for p in uniq for _ in range(24)]
+    batch = Batch(members, device=dev)
+    for m, x in enumerate(batch.inputs):
+        x.copy_(inputs.uniform_complex_device(x.numel(), 1000 + m, torch.complex64, dev))
+    total_bytes = 0.0
+    for p in members:
+        total_bytes += 2 * 3 * 2 * p.buffer_numel(0) * 8  # fwd+bwd, 3 stages, read+write
+    work = {id(p): p.workspace() for p in uniq}
+
+    def per_transform():
+        for m, p in enumerate(members):
+            p.forward(batch.inputs[m], out=batch.outputs[m], work=work[id(p)])
+        for m, p in enumerate(members):
+            p.backward(batch.outputs[m], out=batch.inputs[m], work=work[id(p)])
+
+    def batched():
+        batch.forward()
+        batch.backward()
+
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        batched()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            batched()
+    torch.cuda.synchronize()
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    t_graph = timeit(graph.replay)
+    t_batch = timeit(batched)
+    t_plain = timeit(per_transform)
+    out = {"metric": "fwd+bwd ms, 168 mixed complex64 transforms; batched vs per-transform",
+           "value": round(t_graph, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_graph, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "7 shapes x 8 instances x 3 components c2c complex64, mixed slab/pencil grids",
+                      "shapes": [[list(s), list(g)] for s, g in BATCH_SHAPES]},
+           "batched_graph_ms": round(t_graph, 3), "batched_eager_ms": round(t_batch, 3),
+           "per_transform_ms": round(t_plain, 3), "algorithmic_bytes": total_bytes,
+           "pct_hbm_peak": round(100.0 * total_bytes / (t_graph * 1e-3) / HBM_PEAK, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -106,6 +184,9 @@ def main():
     from paper_1804_09536_amd import inputs
     from paper_1804_09536_amd.plan import Plan
 
+    if args.workload == "batch168":
+        bench_batch(args)
+        return
     shape, grid, kind, prec, chain = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

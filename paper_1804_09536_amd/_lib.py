@@ -68,6 +68,13 @@ def load():
         "pfft_bind_device_state": [vp, vp, vp],
         "pfft_workspace_bytes": [vp, ctypes.POINTER(sz)],
         "pfft_redistribute": [vp, c_int, c_int, vp, vp, vp],
+        "pfft_batch_create": [ctypes.POINTER(vp), c_int, ctypes.POINTER(vp)],
+        "pfft_batch_destroy": [vp],
+        "pfft_batch_buffer_bytes": [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "pfft_batch_member_offsets": [vp, c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "pfft_batch_device_state_bytes": [vp, ctypes.POINTER(sz)],
+        "pfft_batch_bind": [vp, vp, vp, vp, vp, vp],
+        "pfft_batch_execute": [vp, c_int, vp],
         "pfft_forward": [vp, vp, vp, vp, vp],
         "pfft_backward": [vp, vp, vp, vp, vp],
         "pfft_adjoint_forward": [vp, vp, vp, vp, vp],

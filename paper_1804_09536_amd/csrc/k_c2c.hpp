@@ -135,10 +135,10 @@ struct C2CWorker {
 
     // Transform the registers of one tile (LDS-staged passes), scale, store.
     __device__ __forceinline__ void process(const StageArgs &a, T2 (&v)[NL][P], const SideAddr<P> &dst, int count,
-                                            T2 *lds) const
+                                            T2 *lds, const T2 *tw) const
     {
         if constexpr (fft_npasses(N) > 1) __syncthreads();  // the previous tile's last LDS reads are done
-        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, (const T2 *)a.twiddle);
+        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, tw);
         const T scale = (T)a.scale;
         if (scale != (T)1) {
 #pragma unroll
@@ -184,6 +184,29 @@ constexpr int c2c_waves_per_eu()
     return (S::NT == 512 && S::H > 1) ? 4 : 1;
 }
 
+// Twiddle table of the stage staged in LDS once per workgroup (the passes
+// then read twiddles with LDS instead of vector-memory instructions).
+#ifndef PFFT_TWIDDLES_IN_LDS
+#define PFFT_TWIDDLES_IN_LDS 0
+#endif
+template <typename T2, int N>
+struct TwiddleStage {
+    static constexpr bool on = PFFT_TWIDDLES_IN_LDS && fft_npasses(N) > 1;
+    static constexpr int SIZE = on ? N : 1;
+    __device__ static __forceinline__ const T2 *stage(T2 *buf, const void *tw)
+    {
+        if constexpr (on) {
+            const T2 *g = (const T2 *)tw;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) buf[i] = g[i];
+            __syncthreads();
+            return buf;
+        } else {
+            (void)buf;
+            return (const T2 *)tw;
+        }
+    }
+};
+
 template <typename T, int N, bool CONTIG, int SIGN, class S>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c(
     StageArgs a)
@@ -192,6 +215,8 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     using T2 = typename Wk::T2;
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];
+    __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
+    const T2 *tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);
     Wk wk;
     wk.init_geometry();
     const long G = gridDim.x, nt = a.ntiles;
@@ -201,7 +226,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     for (long ti = blockIdx.x; ti < nt; ti += G) {
         wk.refresh();
         wk.load(a, a.tiles[ti], v, d, c);
-        wk.process(a, v, d, c, lds);
+        wk.process(a, v, d, c, lds, tw);
     }
 }
 
@@ -226,7 +251,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
         const StageArgs &a = args[(unsigned)t.flags >> 8];
         wk.refresh();
         wk.load(a, t, v, d, c);
-        wk.process(a, v, d, c, lds);
+        wk.process(a, v, d, c, lds, (const T2 *)a.twiddle);
     }
 }
 

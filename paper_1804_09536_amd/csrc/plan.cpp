@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -829,7 +830,12 @@ struct BatchGroup {
 }  // namespace pfft
 
 struct pfft_batch_s {
-    std::vector<pfft_plan_s *> plans;
+    std::vector<pfft_plan_s *> plans;  // members (pointers into `owned`)
+    std::vector<pfft_plan_s *> owned;  // private copies of the distinct plans
+    ~pfft_batch_s()
+    {
+        for (auto *p : owned) delete p;
+    }
     int precision = 0;
     std::vector<size_t> in_off, out_off, work_off, blob_off;
     size_t in_bytes = 0, out_bytes = 0, work_bytes = 0;
@@ -868,8 +874,15 @@ static int batch_plan(pfft_batch_s *b)
         b->in_bytes += align256(std::max(ib, ob));
         b->out_bytes += align256(std::max(ib, ob));
         b->work_bytes += align256(p->spec_bytes) * (p->kind == PFFT_R2C ? 2 : 1);
-        b->blob_off.push_back(blob_reserve(b->blob, p->blob.size()));
-        memcpy(b->blob.data() + b->blob_off.back(), p->blob.data(), p->blob.size());
+        // members that are the same plan share one copy of its tables
+        size_t off = SIZE_MAX;
+        for (int q = 0; q < m; q++)
+            if (b->plans[q] == p) off = b->blob_off[q];
+        if (off == SIZE_MAX) {
+            off = blob_reserve(b->blob, p->blob.size());
+            memcpy(b->blob.data() + off, p->blob.data(), p->blob.size());
+        }
+        b->blob_off.push_back(off);
     }
     for (int dir = 0; dir < 2; dir++) {
         size_t maxk = 0;
@@ -1250,7 +1263,18 @@ int pfft_batch_create(pfft_batch *out, int nplans, const pfft_plan *plans)
             delete b;
             return fail(PFFT_EDTYPE, "batch members must share one precision");
         }
-        b->plans.push_back(plans[i]);
+        pfft_plan_s *copy = nullptr;
+        for (int q = 0; q < i; q++)
+            if (plans[q] == plans[i]) copy = b->plans[q];
+        if (!copy) {
+            copy = new pfft_plan_s(*plans[i]);
+            copy->prof.clear();
+            copy->pool.clear();
+            copy->profiling = false;
+            copy->dev = nullptr;
+            b->owned.push_back(copy);
+        }
+        b->plans.push_back(copy);
     }
     b->precision = plans[0]->precision;
     int rc = batch_plan(b);

@@ -57,3 +57,17 @@ def local_index_fill(block_sizes) -> np.ndarray:
     parts = [np.arange(int(c), dtype=np.float64) for c in block_sizes]
     j = np.concatenate(parts) if parts else np.zeros(0)
     return (j + 1j * j).astype(np.complex128)
+
+
+def uniform_complex_device(n: int, seed: int, dtype, device):
+    """Device-side variant for multi-gigabyte timing inputs: real and
+    imaginary parts i.i.d. U[-1, 1] from torch's generator seeded with
+    `seed` (a different stream from the numpy recipe above; used only where
+    values are not compared with the oracle)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    buf = torch.rand(2 * n, dtype=rdt, device=device, generator=g).mul_(2.0).sub_(1.0)
+    return torch.view_as_complex(buf.view(n, 2))

@@ -218,3 +218,54 @@ class Plan:
         check(lib.pfft_redistribute(self._h, layout_from, layout_to, _ptr(x), _ptr(out),
                                     _stream_handle(self.device)), "pfft_redistribute")
         return out
+
+
+class Batch:
+    """Several plans executed together (see pfft_batch_* in include/pfft.h):
+    one launch per (stage, kernel shape) over every member's tiles.  The batch
+    owns one input, one output and one workspace buffer; ``inputs[m]`` and
+    ``outputs[m]`` are views of member m's regions."""
+
+    def __init__(self, plans, device=None):
+        lib = _lib.load()
+        self.plans = list(plans)
+        self.device = torch.device(device if device is not None else self.plans[0].device)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(lib.pfft_batch_create(ctypes.byref(h), len(self.plans), arr), "pfft_batch_create")
+        self._h = h
+        ib, ob, wb, sb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib.pfft_batch_buffer_bytes(h, ctypes.byref(ib), ctypes.byref(ob), ctypes.byref(wb)),
+              "pfft_batch_buffer_bytes")
+        check(lib.pfft_batch_device_state_bytes(h, ctypes.byref(sb)), "pfft_batch_device_state_bytes")
+        self.in_buf = torch.empty(ib.value, dtype=torch.uint8, device=self.device)
+        self.out_buf = torch.empty(ob.value, dtype=torch.uint8, device=self.device)
+        self.work_buf = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.state = torch.empty(max(256, sb.value), dtype=torch.uint8, device=self.device)
+        check(lib.pfft_batch_bind(h, _ptr(self.state), _ptr(self.in_buf), _ptr(self.out_buf), _ptr(self.work_buf),
+                                  _stream_handle(self.device)), "pfft_batch_bind")
+        self.inputs, self.outputs = [], []
+        for m, p in enumerate(self.plans):
+            io, oo = ctypes.c_size_t(), ctypes.c_size_t()
+            check(lib.pfft_batch_member_offsets(h, m, ctypes.byref(io), ctypes.byref(oo)), "pfft_batch_member_offsets")
+            real = p.kind == "r2c"
+            n_in = p.buffer_numel(0, real=real)
+            n_out = p.buffer_numel(p.num_layouts - 1)
+            isz = torch.empty(0, dtype=p.in_dtype).element_size()
+            osz = torch.empty(0, dtype=p.spec_dtype).element_size()
+            self.inputs.append(self.in_buf[io.value:io.value + n_in * isz].view(p.in_dtype))
+            self.outputs.append(self.out_buf[oo.value:oo.value + n_out * osz].view(p.spec_dtype))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.pfft_batch_destroy(h)
+            self._h = None
+
+    def forward(self):
+        """Every member's forward transform: inputs[m] -> outputs[m]."""
+        check(_lib.load().pfft_batch_execute(self._h, 0, _stream_handle(self.device)), "pfft_batch_execute")
+
+    def backward(self):
+        """Every member's backward transform: outputs[m] -> inputs[m]."""
+        check(_lib.load().pfft_batch_execute(self._h, 1, _stream_handle(self.device)), "pfft_batch_execute")

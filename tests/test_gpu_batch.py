@@ -1,0 +1,85 @@
+"""Batched execution: several plans of different shapes and grids in one
+batch give the same results as their own per-transform launches (the same
+kernels, bit for bit) and as the oracle; a captured graph replays them."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_09536_amd import inputs
+from paper_1804_09536_amd.plan import Batch, Plan
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [
+    ((16, 32, 8), (3, 5), "c2c"),
+    ((32, 16, 64), (2, 4), "c2c"),
+    ((24, 12, 48), (2, 2), "c2c"),       # radix-3 lengths
+    ((32, 32, 32), (4,), "c2c"),         # slab
+    ((8, 16, 4, 32), (3, 1, 5), "c2c"),  # 4-D
+    ((16, 16, 32), (4, 2), "r2c"),       # real input (per-member launches inside the batch)
+]
+
+
+def _fill(batch):
+    data = []
+    for m, p in enumerate(batch.plans):
+        n = batch.inputs[m].numel()
+        if p.kind == "c2c":
+            u = inputs.uniform_complex(n, [30, m], np.complex64)
+        else:
+            u = inputs.gaussian_real(n, [30, m], np.float32)
+        batch.inputs[m].copy_(torch.from_numpy(u))
+        data.append(u)
+    return data
+
+
+def test_batch_equals_per_transform_and_oracle():
+    plans = [Plan(s, g, kind=k) for s, g, k in MEMBERS]
+    plans.append(plans[1])  # the same plan twice shares its tables
+    b = Batch(plans)
+    data = _fill(b)
+    b.forward()
+    torch.cuda.synchronize()
+    for m, p in enumerate(b.plans):
+        print("member", m, p.shape, p.grid, p.kind, flush=True)
+        ref = p.forward(torch.from_numpy(data[m]).cuda())
+        torch.cuda.synchronize()
+        assert b.outputs[m].cpu().numpy().tobytes() == ref.cpu().numpy().tobytes()
+        ch = oracle.Chain.paper(p.shape, p.grid, kind=p.kind)
+        expect = oracle.forward(ch, data[m].astype(np.complex128 if p.kind == "c2c" else np.float64))
+        got = b.outputs[m].cpu().numpy()
+        assert np.linalg.norm(got - expect) / np.linalg.norm(expect) <= 1e-5
+    b.backward()
+    torch.cuda.synchronize()
+    for m in range(len(b.plans)):
+        back = b.inputs[m].cpu().numpy()
+        assert np.linalg.norm(back - data[m]) / np.linalg.norm(data[m]) <= 1e-5
+
+
+def test_batch_graph_replay():
+    plans = [Plan(s, g, kind=k) for s, g, k in MEMBERS[:3]]
+    b = Batch(plans)
+    data = _fill(b)
+    b.forward()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in b.outputs]
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            b.forward()
+    torch.cuda.current_stream().wait_stream(stream)
+    for rep in range(3):
+        for o in b.outputs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for m in range(len(plans)):
+            assert torch.equal(b.outputs[m], eager[m]), (rep, m)
+        # eager work between replays
+        for m in range(len(plans)):
+            b.inputs[m].copy_(torch.from_numpy(data[m]))
+        torch.cuda.synchronize()
