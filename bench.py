@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pencil512", choices=sorted(WORKLOADS) + ["batch168"])
+    ap.add_argument("--workload", default="pencil512", choices=sorted(WORKLOADS) + ["batch168", "grad256"])
     ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
@@ -172,6 +172,64 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_grad(args):
+    """The differentiation workload: loss = sum_k |k|^2 |FFT(u)(k)|^2 on a
+    256^3 float32 field (r2c, 4x4 pencil); one autograd step (forward, loss,
+    backward through the adjoint kernels) against one plain forward+backward
+    of the same plan."""
+    import numpy as np
+    import torch
+
+    from paper_1804_09536_amd import autograd as pad
+    from paper_1804_09536_amd import inputs
+    from paper_1804_09536_amd.plan import Plan
+
+    dev = torch.device("cuda:0")
+    shape, grid = (256, 256, 256), (4, 4)
+    plan = Plan(shape, grid, kind="r2c", device=dev).bind()
+    w = pad.wavenumber_weight(plan).to(torch.float32)
+    u0 = torch.from_numpy(inputs.gaussian_real(plan.buffer_numel(0, real=True), [5], np.float32)).to(dev)
+    u = u0.clone().requires_grad_()
+
+    def grad_step():
+        u.grad = None
+        uh = pad.forward(u, plan)
+        loss = torch.sum(w * (uh.real * uh.real + uh.imag * uh.imag))
+        loss.backward()
+
+    y = plan.empty(plan.num_layouts - 1)
+    z = plan.empty(0, real=True)
+
+    def plain_step():
+        plan.forward(u0, out=y)
+        plan.backward(y, out=z)
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    t_grad = timeit(grad_step)
+    t_plain = timeit(plain_step)
+    spec = plan.buffer_numel(plan.num_layouts - 1) * 8
+    real = plan.buffer_numel(0, real=True) * 4
+    # r2c stage: real in + spectrum out; two complex stages: spectrum in + out; same for the adjoint
+    step_bytes = 2 * ((real + spec) + 2 * (2 * spec))
+    out = {"metric": "autograd step (forward + loss + adjoint) vs plain fwd+bwd, 256^3 r2c float32",
+           "value": round(t_grad, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_grad, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256x256x256 r2c float32, 4x4 pencil, loss sum |k|^2 |u_hat|^2"},
+           "autograd_step_ms": round(t_grad, 4), "plain_fwd_bwd_ms": round(t_plain, 4),
+           "transform_bytes_per_step": step_bytes}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -186,6 +244,9 @@ def main():
 
     if args.workload == "batch168":
         bench_batch(args)
+        return
+    if args.workload == "grad256":
+        bench_grad(args)
         return
     shape, grid, kind, prec, chain = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

@@ -18,13 +18,17 @@ int resident_workgroups(const void *kernel, int nt)
 int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConfig *cfg)
 {
     switch (kind) {
-    case KIND_C2C:
-        return prec == 0 ? c2c_config_f32(N, contig, variant, cfg) : c2c_config_f64(N, contig, variant, cfg);
+    case KIND_C2C: {
+        int rc = prec == 0 ? c2c_config_f32(N, contig, variant, cfg) : c2c_config_f64(N, contig, variant, cfg);
+        return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
+    }
     case KIND_COPY: return copy_config(N, cfg);
     case KIND_R2C:
-    case KIND_C2R:
+    case KIND_C2R: {
         if (!contig) return -1;
-        return real_config(prec, N, kind, cfg);
+        int rc = (N % 2 == 0) ? real_config(prec, N, kind, cfg) : -1;
+        return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
+    }
     default: return -1;
     }
 }
@@ -32,6 +36,7 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
 int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelConfig &cfg, size_t esize,
                  const StageArgs &a, hipStream_t s)
 {
+    if (cfg.id < 0 && kind != KIND_COPY) return (int)dft_launch(prec, N, kind, contig, sign, cfg, a, s);
     switch (kind) {
     case KIND_C2C:
         return (int)(prec == 0 ? c2c_launch_f32(N, contig, sign, cfg, a, s) : c2c_launch_f64(N, contig, sign, cfg, a, s));

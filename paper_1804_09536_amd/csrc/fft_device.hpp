@@ -266,9 +266,12 @@ __device__ __forceinline__ int pass_out_index(int jt, int b, int s)
 // LDS addressing of a tile of W lines of N points.
 //  strided tiles: point-major, lines contiguous, rows padded by 16 bytes;
 //  contiguous tiles: line-major, one pad element after every 8 points.
+#ifndef PFFT_STRIDED_PAD_BYTES
+#define PFFT_STRIDED_PAD_BYTES 16
+#endif
 template <typename T2, int N, int W, bool CONTIG>
 struct LdsTile {
-    static constexpr int PADW = 16 / (int)sizeof(T2) > 0 ? 16 / (int)sizeof(T2) : 1;
+    static constexpr int PADW = PFFT_STRIDED_PAD_BYTES / (int)sizeof(T2);
     static constexpr int ROW = W + PADW;
     static constexpr int LINE = N + N / 8;
     static constexpr int SIZE = CONTIG ? W * LINE : N * ROW;

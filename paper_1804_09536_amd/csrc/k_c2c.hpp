@@ -187,11 +187,11 @@ constexpr int c2c_waves_per_eu()
 // Twiddle table of the stage staged in LDS once per workgroup (the passes
 // then read twiddles with LDS instead of vector-memory instructions).
 #ifndef PFFT_TWIDDLES_IN_LDS
-#define PFFT_TWIDDLES_IN_LDS 0
+#define PFFT_TWIDDLES_IN_LDS 1
 #endif
 template <typename T2, int N>
 struct TwiddleStage {
-    static constexpr bool on = PFFT_TWIDDLES_IN_LDS && fft_npasses(N) > 1;
+    static constexpr bool on = PFFT_TWIDDLES_IN_LDS && fft_npasses(N) > 1 && N * sizeof(T2) <= 8192;
     static constexpr int SIZE = on ? N : 1;
     __device__ static __forceinline__ const T2 *stage(T2 *buf, const void *tw)
     {

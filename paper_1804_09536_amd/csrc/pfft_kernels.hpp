@@ -14,7 +14,8 @@ namespace pfft {
 struct KernelConfig {
     int W = 0;
     int threads = 0;
-    int id = 0;        // tile-shape variant: 0 default, 1 half the lines per tile, 2 double
+    int id = 0;        // tile-shape variant (0 default, 1 half, 2 double, 3 double in two LDS portions);
+                       // -1: direct-sum DFT kernel (lengths without a radix plan)
     int resident = 0;  // 1: grid = resident workgroups looping over tiles; 0: one tile per workgroup
 };
 
@@ -40,6 +41,9 @@ hipError_t c2c_launch_multi_f64(int N, int contig, int sign, const KernelConfig 
 int copy_config(int N, KernelConfig *cfg);
 hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int real_config(int prec, int N, int kind, KernelConfig *cfg);
+int dft_config(int prec, int N, int kind, KernelConfig *cfg);
+hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
+                      hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 
 }  // namespace pfft

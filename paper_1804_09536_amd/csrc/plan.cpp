@@ -894,10 +894,11 @@ static int batch_plan(pfft_batch_s *b)
                 if (k >= list.size()) continue;
                 const Launch &ln = list[k];
                 BatchGroup *g = nullptr;
-                if (ln.kind == KIND_C2C)
+                const bool multi = ln.kind == KIND_C2C && ln.cfg.id >= 0;  // a multi-transform kernel exists
+                if (multi)
                     for (auto &x : gs)
-                        if (x.kind == KIND_C2C && x.N == ln.N && x.contig == ln.contig && x.cfg.id == ln.cfg.id &&
-                            x.cfg.resident == ln.cfg.resident)
+                        if (x.kind == KIND_C2C && x.cfg.id >= 0 && x.N == ln.N && x.contig == ln.contig &&
+                            x.cfg.id == ln.cfg.id && x.cfg.resident == ln.cfg.resident)
                             g = &x;
                 if (!g) {
                     gs.emplace_back();
@@ -911,7 +912,7 @@ static int batch_plan(pfft_batch_s *b)
                 g->members.push_back(m);
             }
             for (auto &g : gs) {
-                if (g.kind == KIND_C2C) {
+                if (g.kind == KIND_C2C && g.cfg.id >= 0) {
                     int64_t nt = 0;
                     for (int m : g.members) nt += (dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd)[k].ntiles;
                     if ((int64_t)g.members.size() >= (1 << 23)) return fail(PFFT_EINVAL, "too many batch members");
@@ -943,7 +944,7 @@ static void batch_fill_args(pfft_batch_s *b)
     const uint8_t *dev = (const uint8_t *)b->dev;
     for (int dir = 0; dir < 2; dir++) {
         for (auto &g : b->groups[dir]) {
-            if (g.kind != KIND_C2C) continue;
+            if (g.kind != KIND_C2C || g.cfg.id < 0) continue;
             StageArgs *args = (StageArgs *)(b->blob.data() + g.off_args);
             for (size_t mi = 0; mi < g.members.size(); mi++) {
                 const int m = g.members[mi];
@@ -1348,7 +1349,7 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
     const uint8_t *dev = (const uint8_t *)b->dev;
     const int sign = direction == 0 ? -1 : 1;
     for (const auto &g : b->groups[direction]) {
-        if (g.kind == KIND_C2C) {
+        if (g.kind == KIND_C2C && g.cfg.id >= 0) {
             if (g.ntiles == 0) continue;
             const StageArgs *args = (const StageArgs *)(dev + g.off_args);
             const Tile *tiles = (const Tile *)(dev + g.off_tiles);

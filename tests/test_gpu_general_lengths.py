@@ -1,0 +1,60 @@
+"""Lengths without a radix-2/3 plan run through the direct-sum kernel: the
+paper's two appendix programs on the GPU (42x127x256 on 2-D grids and
+16x17x18x19 on 3-D grids, complex128, filled with j + j*I, forward then
+backward to 1e-8), their forward results against the oracle, and odd-length
+real transforms."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_09536_amd import inputs
+from paper_1804_09536_amd.plan import Plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape,grid", [((42, 127, 256), (2, 2)), ((42, 127, 256), (3, 4)),
+                                        ((16, 17, 18, 19), (2, 2, 2)), ((16, 17, 18, 19), (1, 2, 3))])
+def test_appendix_programs_on_gpu(shape, grid):
+    print("case", shape, grid, flush=True)
+    p = Plan(shape, grid, precision="f64")
+    ch = oracle.Chain.paper(shape, grid)
+    P = int(np.prod(grid))
+    sizes = [int(np.prod(p.local_block(0, r)[0])) for r in range(P)]
+    a = inputs.local_index_fill(sizes)
+    y = p.forward(torch.from_numpy(a).cuda())
+    z = _host(p.backward(y))
+    j = a.real
+    assert np.all(np.abs(z.real - j) < 1e-8) and np.all(np.abs(z.imag - j) < 1e-8)
+    got = _host(y)
+    expect = oracle.forward(ch, a)
+    assert np.linalg.norm(got - expect) / np.linalg.norm(expect) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,grid,prec", [((9, 10, 15), (2, 2), "f64"), ((8, 6, 7), (2,), "f64"),
+                                             ((12, 20, 14), (3, 2), "f32"), ((5, 7, 6), (2, 3), "f32")])
+def test_general_length_real_and_complex(shape, grid, prec):
+    print("case", shape, grid, prec, flush=True)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for kind in ("c2c", "r2c"):
+        p = Plan(shape, grid, precision=prec, kind=kind)
+        ch = oracle.Chain.paper(shape, grid, kind=kind)
+        if kind == "c2c":
+            x = inputs.uniform_complex(p.buffer_numel(0), [40], np.complex64 if prec == "f32" else np.complex128)
+            x64 = x.astype(np.complex128)
+        else:
+            x = inputs.gaussian_real(p.buffer_numel(0, real=True), [40], np.float32 if prec == "f32" else np.float64)
+            x64 = x.astype(np.float64)
+        y = p.forward(torch.from_numpy(x).cuda())
+        got = _host(y)
+        assert np.linalg.norm(got - oracle.forward(ch, x64)) / np.linalg.norm(got) <= tol
+        back = _host(p.backward(y))
+        assert np.linalg.norm(back - oracle.backward(ch, got.astype(np.complex128))) / np.linalg.norm(back) <= tol
+        adj = _host(p.adjoint_forward(y))
+        assert np.linalg.norm(adj - oracle.adjoint_forward(ch, got.astype(np.complex128))) / np.linalg.norm(adj) <= tol
