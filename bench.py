@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
-    ap.add_argument("--placement", default="gather", choices=["gather", "scatter"])
+    ap.add_argument("--placement", default="gather", choices=["gather", "scatter", "direct", "final"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy one buffer of the workload's size with torch (a "
                          "known-size reference for hardware byte counters)")

@@ -69,9 +69,14 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_PATH_UNFUSED 1u      /* standalone redistribution kernel, then transform in place of the new layout */
 #define PFFT_PATH_PACK_REALIGN 2u /* traditional method: local transpose, contiguous exchange, realign (Sec. 3.2.1) */
 #define PFFT_PATH_MASK 3u
-#define PFFT_PLACE_SCATTER 8u     /* fused path: each partial transform writes its result straight into the
-                                     layout of the next one (redistribution fused into the store) instead of
-                                     its own layout (fused into the next load); same results */
+/* Placement of intermediate results on the fused path (at most one; same results, different
+   access patterns).  Default: each partial transform leaves its result in the layout where it
+   was computed and the next one gathers (redistribution fused into the load). */
+#define PFFT_PLACE_SCATTER 8u     /* into the next partial transform's layout (fused into the store) */
+#define PFFT_PLACE_DIRECT 16u     /* first result in its own layout, every later one straight into the
+                                     direction's final layout: the intermediate alignments of the chain are
+                                     never stored, consecutive exchanges fuse into one stage */
+#define PFFT_PLACE_FINAL 32u      /* every result straight into the direction's final layout */
 #define PFFT_LAYOUTS_ONLY 4u      /* plan layouts and redistributions only: no transform kernels are
                                      set up (any lengths), pfft_forward & co. return PFFT_EUNSUPPORTED */
 
@@ -102,7 +107,7 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *     before the step).  Initially direction i splits axis i.
  *   nsteps: number of chain steps (ignored when chain is NULL).
  *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
- *     or-ed with PFFT_PLACE_SCATTER and PFFT_LAYOUTS_ONLY.
+ *     or-ed with one PFFT_PLACE_* and with PFFT_LAYOUTS_ONLY.
  * The chain must leave every axis transformed (each axis whole in some
  * layout).  For PFFT_R2C the last axis must be whole in layout 0.
  * Returns PFFT_OK and *out, or an error (then *out is NULL).

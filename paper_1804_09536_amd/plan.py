@@ -42,9 +42,12 @@ class Plan:
           (local transpose + contiguous exchange + realign).
     layouts_only: plan layouts and redistributions only (any lengths); the
           transforms then raise.
-    placement: "gather" (each partial transform's result stays in its own
-          layout; the next one gathers) or "scatter" (written straight into
-          the next one's layout).  Same results; different access patterns.
+    placement: where partial results are stored on the fused path: "gather"
+          (in the layout where they were computed; the next stage gathers),
+          "scatter" (in the next stage's layout), "direct" (the first in its
+          own layout, later ones in the final layout: the chain's middle
+          alignments are never stored) or "final" (all in the final layout).
+          Same results; different access patterns.
     """
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
@@ -68,7 +71,7 @@ class Plan:
         st = lib.pfft_plan_create(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd,
                                   0 if precision == "f32" else 1, 0 if kind == "c2c" else 1, NORMS[norm],
                                   ch, nsteps, PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0)
-                                  | (_lib.PFFT_PLACE_SCATTER if placement == "scatter" else 0))
+                                  | _lib.PLACEMENTS[placement])
         check(st, "pfft_plan_create")
         self._h = h
         n = ctypes.c_int()

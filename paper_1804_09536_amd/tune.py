@@ -64,7 +64,7 @@ def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None,
     if key in table and not force:
         return table[key]
     best = None
-    for placement in ("gather", "scatter"):
+    for placement in ("gather", "scatter", "direct", "final"):
         plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path, placement=placement)
         real = kind == "r2c"
         n = plan.buffer_numel(0, real=real)
