@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--path", default="fused", choices=["fused", "unfused", "pack_realign"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
-    ap.add_argument("--placement", default="gather", choices=["gather", "scatter", "direct", "final"])
+    ap.add_argument("--placement", default=None,
+                    help="gather|scatter|direct|final, or FWD,BWD (default: the library's default pair)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy one buffer of the workload's size with torch (a "
                          "known-size reference for hardware byte counters)")
@@ -251,8 +252,11 @@ def main():
     shape, grid, kind, prec, chain = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    placement = tuple(args.placement.split(",")) if args.placement else Plan.DEFAULT_PLACEMENT
+    if len(placement) == 1:
+        placement = placement * 2
     plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev,
-                placement=args.placement).bind()
+                placement=placement).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
     if kind == "c2c":
         u_np = inputs.uniform_complex(n_in, [4], np.complex64 if prec == "f32" else np.complex128)
@@ -301,7 +305,7 @@ def main():
         avg_ms = d["ms"] / d["n"]
         per_launch = d["bytes"] / d["n"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(dom) if (args.workload == "pencil512" and args.placement == "gather"
+        traffic = measured_traffic(dom) if (args.workload == "pencil512" and args.placement is None
                                             and args.path == "fused") else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": 8000.0,
                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
@@ -337,7 +341,7 @@ def main():
                                % ("x".join(map(str, shape)), kind, "complex64" if prec == "f32" else "complex128",
                                   "x".join(map(str, grid)), args.path),
                    "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path,
-                   "placement": args.placement, "tuning": plan.tuning()},
+                   "placement": list(plan.placement), "tuning": plan.tuning()},
         "step_bytes": step_bytes,
         "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
         "roundtrip_rel_l2": rt,

@@ -69,14 +69,21 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_PATH_UNFUSED 1u      /* standalone redistribution kernel, then transform in place of the new layout */
 #define PFFT_PATH_PACK_REALIGN 2u /* traditional method: local transpose, contiguous exchange, realign (Sec. 3.2.1) */
 #define PFFT_PATH_MASK 3u
-/* Placement of intermediate results on the fused path (at most one; same results, different
-   access patterns).  Default: each partial transform leaves its result in the layout where it
-   was computed and the next one gathers (redistribution fused into the load). */
-#define PFFT_PLACE_SCATTER 8u     /* into the next partial transform's layout (fused into the store) */
-#define PFFT_PLACE_DIRECT 16u     /* first result in its own layout, every later one straight into the
-                                     direction's final layout: the intermediate alignments of the chain are
-                                     never stored, consecutive exchanges fuse into one stage */
-#define PFFT_PLACE_FINAL 32u      /* every result straight into the direction's final layout */
+/* Placement of intermediate results on the fused path, chosen separately for the forward
+   (bits 3-4) and the backward (bits 5-6) chain; same results, different access patterns.
+   GATHER (0): each partial transform leaves its result in the layout where it was computed and
+   the next one gathers (redistribution fused into the load).  SCATTER: into the next partial
+   transform's layout (fused into the store).  DIRECT: the first result in its own layout, every
+   later one straight into the chain's final layout (the middle alignments are never stored and
+   consecutive exchanges fuse into one stage).  FINAL: every result into the final layout. */
+#define PFFT_PLACE_SCATTER (1u << 3)
+#define PFFT_PLACE_DIRECT (2u << 3)
+#define PFFT_PLACE_FINAL (3u << 3)
+#define PFFT_PLACE_MASK (3u << 3)
+#define PFFT_PLACE_BWD_SCATTER (1u << 5)
+#define PFFT_PLACE_BWD_DIRECT (2u << 5)
+#define PFFT_PLACE_BWD_FINAL (3u << 5)
+#define PFFT_PLACE_BWD_MASK (3u << 5)
 #define PFFT_LAYOUTS_ONLY 4u      /* plan layouts and redistributions only: no transform kernels are
                                      set up (any lengths), pfft_forward & co. return PFFT_EUNSUPPORTED */
 
@@ -107,7 +114,8 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *     before the step).  Initially direction i splits axis i.
  *   nsteps: number of chain steps (ignored when chain is NULL).
  *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
- *     or-ed with one PFFT_PLACE_* and with PFFT_LAYOUTS_ONLY.
+ *     or-ed with one forward and one backward placement (PFFT_PLACE_*,
+ *     PFFT_PLACE_BWD_*) and with PFFT_LAYOUTS_ONLY.
  * The chain must leave every axis transformed (each axis whole in some
  * layout).  For PFFT_R2C the last axis must be whole in layout 0.
  * Returns PFFT_OK and *out, or an error (then *out is NULL).
@@ -120,8 +128,10 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
  * Performance knobs of a plan (results never change).  tile_*: 0 default
  * lines per tile, 1 half as many (more workgroups per CU), 2 twice as many
  * (wider coalesced rows, more LDS), 3 twice as many exchanged through the
- * default LDS in two portions (wider rows at the default LDS size; lengths
- * without this shape use the default); resident_*: 1 launches only as many
+ * default LDS in two portions (wider rows at the default LDS size), 4 four
+ * times as many with 1024-thread workgroups exchanged in two portions
+ * (widest rows, one workgroup per CU); lengths without a shape use the
+ * default; resident_*: 1 launches only as many
  * workgroups as the device holds at once, each looping over tiles, 0 one
  * workgroup per tile.  *_contig applies to partial transforms along the last
  * axis, *_strided to the others.  pfft_plan_set_tuning rebuilds the plan's

@@ -65,6 +65,36 @@ __device__ __forceinline__ T2 c_zero()
     return r;
 }
 
+// Streaming (non-temporal) store of a complex value or a pair of them: the
+// data is not read again by this kernel, so it need not occupy the caches.
+template <typename V>
+__device__ __forceinline__ void store_stream(V *p, V v)
+{
+    using E = decltype(v.x);
+    if constexpr (sizeof(V) == 2 * sizeof(E)) {
+        typedef E n2 __attribute__((ext_vector_type(2)));
+        n2 t = {v.x, v.y};
+        __builtin_nontemporal_store(t, (n2 *)p);
+    } else {
+        typedef E n4 __attribute__((ext_vector_type(4)));
+        n4 t = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(t, (n4 *)p);
+    }
+}
+
+// Streaming (non-temporal) load of one complex value.
+template <typename V>
+__device__ __forceinline__ V load_stream(const V *p)
+{
+    using E = decltype(p->x);
+    typedef E n2 __attribute__((ext_vector_type(2)));
+    n2 t = __builtin_nontemporal_load((const n2 *)p);
+    V v;
+    v.x = t.x;
+    v.y = t.y;
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Radix-R DFT in registers, R = 1, 2, 4, 8, 16:  a_s <- sum_r a_r w^{SIGN r s},
 // w = e^{2 pi i / R}.  Built by even/odd splitting; multiplications by the

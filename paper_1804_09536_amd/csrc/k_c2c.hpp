@@ -107,7 +107,13 @@ struct C2CWorker {
         src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
         dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
         const T2 *__restrict__ in = (const T2 *)a.src;
-        if (fast) {
+        if (fast && CONTIG && a.side[0].R == 0) {
+            // whole source lines along the last axis: streaming loads
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++) v[l][m] = load_stream(in + src.off[m] + wl[l] * src.stride[m]);
+        } else if (fast) {
 #pragma unroll
             for (int l = 0; l < NL; l += VEC)
 #pragma unroll
@@ -147,7 +153,16 @@ struct C2CWorker {
                 for (int m = 0; m < P; m++) v[l][m] = c_scale(v[l][m], scale);
         }
         T2 *__restrict__ out = (T2 *)a.dst;
-        if (count > 0) {
+        // Whole destination lines along the last axis are written with
+        // streaming stores (measured faster); rows of strided tiles and line
+        // segments scattered over several blocks with ordinary stores.
+        const bool stream = CONTIG && a.side[1].R == 0;
+        if (count > 0 && stream) {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++) store_stream(out + dst.off[m] + wl[l] * dst.stride[m], v[l][m]);
+        } else if (count > 0) {
 #pragma unroll
             for (int l = 0; l < NL; l += VEC)
 #pragma unroll

@@ -25,12 +25,20 @@ struct C2CVariant {
     static constexpr bool has_half = multi && D::W / 2 >= VEC;
     static constexpr bool has_double = multi && LDS_BYTES_2W <= 150 * 1024;
     static constexpr bool has_split = multi && D::W * 2 <= 128 && (2 * D::NL / 2) % VEC == 0;
-    static constexpr int W = V == 1 && has_half ? D::W / 2 : ((V == 2 && has_double) || (V == 3 && has_split) ? 2 * D::W : D::W);
-    static constexpr int NL0 = (V == 2 && has_double) || (V == 3 && has_split) ? 2 * D::NL : D::NL;
+    // 4: four times the lines, 1024 threads, exchanged in two portions of 2W lines
+    static constexpr bool has_quad = multi && LDS_BYTES_2W <= 150 * 1024 && D::TPL * 4 * D::W / (2 * D::NL) <= 1024 &&
+                                     D::W * 4 <= 256;
+    static constexpr int W = V == 1 && has_half ? D::W / 2
+                             : ((V == 2 && has_double) || (V == 3 && has_split)) ? 2 * D::W
+                             : (V == 4 && has_quad) ? 4 * D::W
+                                                    : D::W;
+    static constexpr int NL0 = (V == 2 && has_double) || (V == 3 && has_split) || (V == 4 && has_quad) ? 2 * D::NL
+                                                                                                         : D::NL;
     static constexpr int NL = (W % NL0 == 0) ? NL0 : VEC;
-    static constexpr int H = V == 3 && has_split ? 2 : 1;
+    static constexpr int H = (V == 3 && has_split) || (V == 4 && has_quad) ? 2 : 1;
     using type = C2CCfg<T, N, CONTIG, W, NL, H>;
-    static constexpr bool exists = V == 0 || (V == 1 && has_half) || (V == 2 && has_double) || (V == 3 && has_split);
+    static constexpr bool exists =
+        V == 0 || (V == 1 && has_half) || (V == 2 && has_double) || (V == 3 && has_split) || (V == 4 && has_quad);
 };
 
 template <typename T, int N, bool CONTIG, int SIGN, int V>
@@ -81,6 +89,10 @@ static hipError_t c2c_launch_multi_s(const KernelConfig &c, const StageArgs *arg
         if constexpr (C2CVariant<T, N, CONTIG, 3>::exists)
             return c2c_launch_multi_v<T, N, CONTIG, SIGN, 3>(c, args, tiles, nt, s);
         break;
+    case 4:
+        if constexpr (C2CVariant<T, N, CONTIG, 4>::exists)
+            return c2c_launch_multi_v<T, N, CONTIG, SIGN, 4>(c, args, tiles, nt, s);
+        break;
     default: break;
     }
     return c2c_launch_multi_v<T, N, CONTIG, SIGN, 0>(c, args, tiles, nt, s);
@@ -98,6 +110,9 @@ static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStr
         break;
     case 3:
         if constexpr (C2CVariant<T, N, CONTIG, 3>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 3>(c, a, s);
+        break;
+    case 4:
+        if constexpr (C2CVariant<T, N, CONTIG, 4>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 4>(c, a, s);
         break;
     default: break;
     }
@@ -120,6 +135,10 @@ static void c2c_cfg_mode(int variant, KernelConfig *c)
         W = C2CVariant<T, N, CONTIG, 3>::type::W;
         NT = C2CVariant<T, N, CONTIG, 3>::type::NT;
         id = 3;
+    } else if (variant == 4 && C2CVariant<T, N, CONTIG, 4>::exists) {
+        W = C2CVariant<T, N, CONTIG, 4>::type::W;
+        NT = C2CVariant<T, N, CONTIG, 4>::type::NT;
+        id = 4;
     } else {
         W = C2CVariant<T, N, CONTIG, 0>::type::W;
         NT = C2CVariant<T, N, CONTIG, 0>::type::NT;

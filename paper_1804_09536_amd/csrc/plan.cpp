@@ -574,19 +574,18 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     // placement of intermediates: in the layout of the stage that made them
     // (the next stage gathers) or in the layout of the stage that uses them
     // (this stage scatters)
-    const bool scatter = (p->flags & PFFT_PLACE_SCATTER) != 0;
-    const bool direct = (p->flags & PFFT_PLACE_DIRECT) != 0;
-    const bool to_final = (p->flags & PFFT_PLACE_FINAL) != 0;
+    const unsigned fwd_place = (p->flags & PFFT_PLACE_MASK) >> 3, bwd_place = (p->flags & PFFT_PLACE_BWD_MASK) >> 5;
     // where stage k of a direction with final layout `fin` leaves its result
-    auto place = [&](int k, int li, int next_li, int fin) {
-        if (k == K - 1 || to_final) return fin;
-        if (direct) return k == 0 ? li : fin;
-        return scatter ? next_li : li;
+    // (placement 0 gather, 1 scatter, 2 direct, 3 final)
+    auto place = [&](unsigned mode, int k, int li, int next_li, int fin) {
+        if (k == K - 1 || mode == 3) return fin;
+        if (mode == 2) return k == 0 ? li : fin;
+        return mode == 1 ? next_li : li;
     };
     int where = (p->kind == PFFT_R2C) ? p->real0 : 0;
     for (int k = 0; k < K; k++) {
         int li = p->sched[k].first, axis = p->sched[k].second;
-        int dst = place(k, li, k + 1 < K ? p->sched[k + 1].first : last, last);
+        int dst = place(fwd_place, k, li, k + 1 < K ? p->sched[k + 1].first : last, last);
         int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : KIND_C2C;
         fsteps.push_back({where, li, dst, axis, kind});
         where = dst;
@@ -594,7 +593,7 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     where = last;
     for (int k = 0; k < K; k++) {
         int li = p->sched[K - 1 - k].first, axis = p->sched[K - 1 - k].second;
-        int dst = place(k, li, k + 1 < K ? p->sched[K - 2 - k].first : 0, 0);
+        int dst = place(bwd_place, k, li, k + 1 < K ? p->sched[K - 2 - k].first : 0, 0);
         int kind = KIND_C2C;
         if (k == K - 1 && p->kind == PFFT_R2C) {
             kind = KIND_C2R;
@@ -1013,10 +1012,8 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
     if (kind != PFFT_C2C && kind != PFFT_R2C) return fail(PFFT_EDTYPE, "bad kind");
     if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
-    const unsigned place_bits = flags & (PFFT_PLACE_SCATTER | PFFT_PLACE_DIRECT | PFFT_PLACE_FINAL);
-    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_SCATTER | PFFT_PLACE_DIRECT | PFFT_PLACE_FINAL)) !=
-            0 ||
-        (flags & PFFT_PATH_MASK) == 3u || (place_bits & (place_bits - 1)) != 0)
+    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK)) != 0 ||
+        (flags & PFFT_PATH_MASK) == 3u)
         return fail(PFFT_EINVAL, "bad flags");
     if (chain && nsteps < 0) return fail(PFFT_EINVAL, "bad nsteps");
     int64_t total = 1;
@@ -1050,7 +1047,7 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
 {
     PFFT_GUARD_BEGIN
     if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
-    if (t->tile_contig < 0 || t->tile_contig > 3 || t->tile_strided < 0 || t->tile_strided > 3 ||
+    if (t->tile_contig < 0 || t->tile_contig > 4 || t->tile_strided < 0 || t->tile_strided > 4 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again

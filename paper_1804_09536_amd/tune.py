@@ -4,8 +4,9 @@ forward+backward on the device with HIP events, and caches the choice in a
 JSON file (``$PFFT_TUNE_CACHE``, default ``~/.cache/paper_1804_09536_amd/tune.json``).
 
 The search is coordinate-wise: strided-stage knobs first (with the library
-defaults for the contiguous stages), then contiguous-stage knobs, for each
-placement; about 30 timed configurations per workload.
+defaults for the contiguous stages), then contiguous-stage knobs, then the
+forward and the backward placement; about 30 timed configurations per
+workload.
 """
 from __future__ import annotations
 
@@ -19,8 +20,9 @@ import torch
 from . import inputs
 from .plan import Plan
 
-TILES = (0, 1, 2, 3)
+TILES = (0, 1, 2, 3, 4)
 RESIDENT = (0, 1)
+PLACEMENTS = ("gather", "scatter", "direct", "final")
 
 
 def cache_path() -> str:
@@ -41,65 +43,102 @@ def _load_cache(path):
         return {}
 
 
-def _time(plan: Plan, x, y, z, work, steps: int) -> float:
+def _time(fn, steps: int) -> float:
     for _ in range(2):
-        plan.forward(x, out=y, work=work)
-        plan.backward(y, out=z, work=work)
+        fn()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        plan.forward(x, out=y, work=work)
-        plan.backward(y, out=z, work=work)
+        fn()
     stop.record()
     stop.synchronize()
     return start.elapsed_time(stop) / steps
 
 
+class _Case:
+    """A plan of the workload with its buffers, for timing."""
+
+    def __init__(self, shape, grid, kind, precision, chain, path, placement):
+        self.plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path, placement=placement)
+        real = kind == "r2c"
+        n = self.plan.buffer_numel(0, real=real)
+        if real:
+            rdt = np.float32 if self.plan.in_dtype == torch.float32 else np.float64
+            self.x = torch.from_numpy(inputs.gaussian_real(n, [0], rdt)).to(self.plan.device)
+        else:
+            self.x = inputs.uniform_complex_device(n, 0, self.plan.spec_dtype, self.plan.device)
+        self.y = self.plan.empty(self.plan.num_layouts - 1)
+        self.z = self.plan.empty(0, real=real)
+        self.work = self.plan.workspace()
+
+    def fwd(self):
+        self.plan.forward(self.x, out=self.y, work=self.work)
+
+    def bwd(self):
+        self.plan.backward(self.y, out=self.z, work=self.work)
+
+    def both(self):
+        self.fwd()
+        self.bwd()
+
+
 def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None, path: str = "fused",
              steps: int = 5, cache: Optional[str] = None, force: bool = False, verbose: bool = False) -> dict:
-    """Best {"placement", "tuning", "ms"} for the workload (cached)."""
+    """Best {"placement": [forward, backward], "tuning", "ms"} for the
+    workload (cached).  Tile knobs are searched with the default placement
+    pair; then each chain's placement is chosen by timing that chain alone
+    (the forward placement changes only forward launches, and likewise)."""
     cache = cache or cache_path()
     key = _key(shape, grid, kind, precision, chain, path)
     table = _load_cache(cache)
     if key in table and not force:
         return table[key]
-    best = None
-    for placement in ("gather", "scatter", "direct", "final"):
-        plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path, placement=placement)
-        real = kind == "r2c"
-        n = plan.buffer_numel(0, real=real)
-        if real:
-            rdt = np.float32 if plan.in_dtype == torch.float32 else np.float64
-            x = torch.from_numpy(inputs.gaussian_real(n, [0], rdt)).to(plan.device)
-        else:
-            x = inputs.uniform_complex_device(n, 0, plan.spec_dtype, plan.device)
-        y = plan.empty(plan.num_layouts - 1)
-        z = plan.empty(0, real=real)
-        work = plan.workspace()
-        cur = plan.tuning()
+    case = _Case(shape, grid, kind, precision, chain, path, None)
+    plan = case.plan
+    cur = plan.tuning()
 
-        def run(t):
-            plan.set_tuning(**t)
-            plan.bind()
-            ms = _time(plan, x, y, z, work, steps)
+    def run(t):
+        plan.set_tuning(**t)
+        plan.bind()
+        ms = _time(case.both, steps)
+        if verbose:
+            print("  tiles %s %.4f ms" % (t, ms), flush=True)
+        return ms
+
+    ms_cur = run(cur)
+    for fields in (("tile_strided", "resident_strided"), ("tile_contig", "resident_contig")):
+        for tile in TILES:
+            for res in RESIDENT:
+                t = dict(cur, **{fields[0]: tile, fields[1]: res})
+                if t == cur:
+                    continue
+                ms = run(t)
+                if ms < ms_cur:
+                    cur, ms_cur = t, ms
+    del case, plan
+    chosen = []
+    for side in (0, 1):
+        best_p, best_ms = None, None
+        for p in PLACEMENTS:
+            c = _Case(shape, grid, kind, precision, chain, path, (p, p))
+            c.plan.set_tuning(**cur)
+            c.plan.bind()
+            if side == 1:
+                c.fwd()
+            ms = _time(c.fwd if side == 0 else c.bwd, steps)
             if verbose:
-                print("  %s %s %.4f ms" % (placement, t, ms), flush=True)
-            return ms
-
-        ms_cur = run(cur)
-        for fields in (("tile_strided", "resident_strided"), ("tile_contig", "resident_contig")):
-            for tile in TILES:
-                for res in RESIDENT:
-                    t = dict(cur, **{fields[0]: tile, fields[1]: res})
-                    if t == cur:
-                        continue
-                    ms = run(t)
-                    if ms < ms_cur:
-                        cur, ms_cur = t, ms
-        if best is None or ms_cur < best["ms"]:
-            best = {"placement": placement, "tuning": cur, "ms": ms_cur}
-        del plan, x, y, z, work
-        torch.cuda.empty_cache()
+                print("  %s placement %s %.4f ms" % ("forward" if side == 0 else "backward", p, ms), flush=True)
+            if best_ms is None or ms < best_ms:
+                best_p, best_ms = p, ms
+            del c
+            torch.cuda.empty_cache()
+        chosen.append(best_p)
+    final = _Case(shape, grid, kind, precision, chain, path, tuple(chosen))
+    final.plan.set_tuning(**cur)
+    final.plan.bind()
+    best = {"placement": chosen, "tuning": cur, "ms": _time(final.both, steps)}
+    del final
+    torch.cuda.empty_cache()
     table = _load_cache(cache)
     table[key] = best
     os.makedirs(os.path.dirname(cache), exist_ok=True)
@@ -114,6 +153,7 @@ def tuned_plan(shape, grid, kind: str = "c2c", precision: str = "f32", chain=Non
                **kw) -> Plan:
     """A plan with the cached (or freshly tuned) best knobs."""
     best = autotune(shape, grid, kind=kind, precision=precision, chain=chain, path=path, **kw)
-    plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path, placement=best["placement"])
+    plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path,
+                placement=tuple(best["placement"]))
     plan.set_tuning(**best["tuning"])
     return plan

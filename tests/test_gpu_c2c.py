@@ -143,9 +143,13 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
     x = _to_dev(u)
     ref = _host(ref_plan.forward(x))
     ref_b = _host(ref_plan.backward(_to_dev(ref)))
-    for placement in ("gather", "scatter", "direct", "final"):
+    names = ("gather", "scatter", "direct", "final")
+    for placement in itertools.product(names, names):
         p = Plan(shape, grid, kind=kind, placement=placement)
-        for tc, ts, rc, rs in itertools.product((0, 1, 2, 3), (0, 1, 2, 3), (0, 1), (0, 1)):
+        # every tile knob with one placement per chain; the default knobs with the mixed pairs
+        knobs = (itertools.product((0, 1, 2, 3, 4), (0, 1, 2, 3, 4), (0, 1), (0, 1))
+                 if placement[0] == placement[1] else [tuple(p.tuning().values())])
+        for tc, ts, rc, rs in knobs:
             p.set_tuning(tile_contig=tc, tile_strided=ts, resident_contig=rc, resident_strided=rs)
             got = _host(p.forward(x))
             assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs)
