@@ -134,7 +134,10 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
  * default; resident_*: 1 launches only as many
  * workgroups as the device holds at once, each looping over tiles, 0 one
  * workgroup per tile.  *_contig applies to partial transforms along the last
- * axis, *_strided to the others.  pfft_plan_set_tuning rebuilds the plan's
+ * axis (tile_contig also to the real-to-complex and complex-to-real stages,
+ * which have shapes 0 and 1 only), *_strided to the others.  Strided tiles
+ * continue over consecutive short runs of lines (inner extents below the
+ * tile width) where the blocks allow it.  pfft_plan_set_tuning rebuilds the plan's
  * tables: query pfft_device_state_bytes again and bind again before use.
  */
 typedef struct {

@@ -26,7 +26,7 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
     case KIND_R2C:
     case KIND_C2R: {
         if (!contig) return -1;
-        int rc = (N % 2 == 0) ? real_config(prec, N, kind, cfg) : -1;
+        int rc = (N % 2 == 0) ? real_config(prec, N, kind, variant, cfg) : -1;
         return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
     }
     default: return -1;

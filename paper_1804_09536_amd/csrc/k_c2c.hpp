@@ -94,6 +94,35 @@ struct C2CWorker {
         }
     }
 
+    // Element offset of each of this thread's lines from line 0 of the tile
+    // (strided mode; stride 1 between lines of a run, ostr between runs).
+    __device__ __forceinline__ void line_offsets(const Tile &t, int s, int (&lo)[NL]) const
+    {
+        if (t.run == 0) {
+#pragma unroll
+            for (int l = 0; l < NL; l++) lo[l] = wl[l];
+            return;
+        }
+        const unsigned run = (unsigned)t.run, b0 = (unsigned)t.b0;
+        const int ostr = t.ostr[s];
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            const unsigned q = b0 + (unsigned)wl[l];
+            const unsigned k = q / run;
+            lo[l] = (int)(q - k * run) + (int)k * ostr;
+        }
+    }
+
+    // Element offset of line l at position m.
+    __device__ __forceinline__ static int at(const SideAddr<P> &sa, const int (&lo)[NL], const int (&wl_)[NL], int l,
+                                             int m)
+    {
+        if constexpr (CONTIG)
+            return sa.off[m] + wl_[l] * sa.stride[m];
+        else
+            return sa.off[m] + lo[l];
+    }
+
     // Compute both sides' addresses of tile `ti` and issue its loads.  A full
     // tile whose addresses are even on both sides (Tile flag bit 0) takes the
     // unpredicated path; others are predicated line by line.
@@ -107,6 +136,8 @@ struct C2CWorker {
         src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
         dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
         const T2 *__restrict__ in = (const T2 *)a.src;
+        int lo[NL];
+        if constexpr (!CONTIG) line_offsets(t, 0, lo);
         if (fast && CONTIG && a.side[0].R == 0) {
             // whole source lines along the last axis: streaming loads
 #pragma unroll
@@ -119,13 +150,13 @@ struct C2CWorker {
 #pragma unroll
                 for (int m = 0; m < P; m++) {
                     if constexpr (VEC == 2) {
-                        T4 q = *(const T4 *)(in + src.off[m] + wl[l]);
+                        T4 q = *(const T4 *)(in + at(src, lo, wl, l, m));
                         v[l][m].x = q.x;
                         v[l][m].y = q.y;
                         v[l + 1][m].x = q.z;
                         v[l + 1][m].y = q.w;
                     } else {
-                        v[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
+                        v[l][m] = in[at(src, lo, wl, l, m)];
                     }
                 }
         } else {
@@ -134,14 +165,14 @@ struct C2CWorker {
             for (int l = 0; l < NL; l++) {
                 const bool ok = wl[l] < cnt;
 #pragma unroll
-                for (int m = 0; m < P; m++) v[l][m] = ok ? in[src.off[m] + wl[l] * src.stride[m]] : c_zero<T2>();
+                for (int m = 0; m < P; m++) v[l][m] = ok ? in[at(src, lo, wl, l, m)] : c_zero<T2>();
             }
         }
     }
 
     // Transform the registers of one tile (LDS-staged passes), scale, store.
-    __device__ __forceinline__ void process(const StageArgs &a, T2 (&v)[NL][P], const SideAddr<P> &dst, int count,
-                                            T2 *lds, const T2 *tw) const
+    __device__ __forceinline__ void process(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], const SideAddr<P> &dst,
+                                            int count, T2 *lds, const T2 *tw) const
     {
         if constexpr (fft_npasses(N) > 1) __syncthreads();  // the previous tile's last LDS reads are done
         fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, tw);
@@ -157,6 +188,8 @@ struct C2CWorker {
         // streaming stores (measured faster); rows of strided tiles and line
         // segments scattered over several blocks with ordinary stores.
         const bool stream = CONTIG && a.side[1].R == 0;
+        int lo[NL];
+        if constexpr (!CONTIG) line_offsets(t, 1, lo);
         if (count > 0 && stream) {
 #pragma unroll
             for (int l = 0; l < NL; l++)
@@ -173,9 +206,9 @@ struct C2CWorker {
                         q.y = v[l][m].y;
                         q.z = v[l + 1][m].x;
                         q.w = v[l + 1][m].y;
-                        *(T4 *)(out + dst.off[m] + wl[l]) = q;
+                        *(T4 *)(out + at(dst, lo, wl, l, m)) = q;
                     } else {
-                        out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+                        out[at(dst, lo, wl, l, m)] = v[l][m];
                     }
                 }
         } else {
@@ -185,7 +218,7 @@ struct C2CWorker {
                 const bool ok = wl[l] < cnt;
 #pragma unroll
                 for (int m = 0; m < P; m++)
-                    if (ok) out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+                    if (ok) out[at(dst, lo, wl, l, m)] = v[l][m];
             }
         }
     }
@@ -240,8 +273,9 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     int c;
     for (long ti = blockIdx.x; ti < nt; ti += G) {
         wk.refresh();
-        wk.load(a, a.tiles[ti], v, d, c);
-        wk.process(a, v, d, c, lds, tw);
+        const Tile &t = a.tiles[ti];
+        wk.load(a, t, v, d, c);
+        wk.process(a, t, v, d, c, lds, tw);
     }
 }
 
@@ -266,7 +300,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
         const StageArgs &a = args[(unsigned)t.flags >> 8];
         wk.refresh();
         wk.load(a, t, v, d, c);
-        wk.process(a, v, d, c, lds, (const T2 *)a.twiddle);
+        wk.process(a, t, v, d, c, lds, (const T2 *)a.twiddle);
     }
 }
 

@@ -12,7 +12,7 @@
 // Flags turn them into each other's adjoints: SF_DOUBLE_INTERIOR doubles the
 // r2c output bins 0 < k < M; SF_HALVE_INTERIOR halves the c2r input bins.
 #include "fft_device.hpp"
-#include "k_c2c.hpp"
+#include "k_c2c_impl.hpp"
 #include "pfft_kernels.hpp"
 
 namespace pfft {
@@ -23,12 +23,12 @@ struct RealLds {
     __device__ static __forceinline__ int idx(int w, int k) { return w * LINE + k + (k >> 3); }
 };
 
-template <typename T, int NR, int KIND>
-__global__ __launch_bounds__((C2CDefault<T, NR / 2, true>::type::NT)) void k_real(StageArgs a)
+// S: the launch shape of the M-point transform (a contiguous-mode C2CCfg).
+template <typename T, int NR, int KIND, class S>
+__global__ __launch_bounds__(S::NT) void k_real(StageArgs a)
 {
     using T2 = typename V2<T>::type;
     constexpr int M = NR / 2;
-    using S = typename C2CDefault<T, M, true>::type;
     constexpr int P = S::P, TPL = S::TPL, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
     using LT = LdsTile<T2, M, W, true>;
     using RL = RealLds<T2, M>;
@@ -172,15 +172,25 @@ __global__ __launch_bounds__((C2CDefault<T, NR / 2, true>::type::NT)) void k_rea
     X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(6) X(12) X(24) X(48) X(96) \
         X(192) X(384) X(768) X(1536) X(3072) X(6144)
 
+// Launch shapes: variant 1 (half the lines per tile) where it exists, else
+// the default.
+template <typename T, int NR>
+struct RealShape {
+    static constexpr bool half = C2CVariant<T, NR / 2, true, 1>::exists;
+    template <int V>
+    using type = typename C2CVariant<T, NR / 2, true, (V == 1 && half) ? 1 : 0>::type;
+};
+
 template <typename T>
-static int real_config_t(int NR, KernelConfig *cfg)
+static int real_config_t(int NR, int variant, KernelConfig *cfg)
 {
+    const int v = variant == 1 ? 1 : 0;
     switch (NR) {
-#define PFFT_CASE(n)                                 \
-    case n:                                          \
-        cfg->W = C2CDefault<T, n / 2, true>::type::W;        \
-        cfg->threads = C2CDefault<T, n / 2, true>::type::NT; \
-        cfg->id = 0;                                 \
+#define PFFT_CASE(n)                                                                              \
+    case n:                                                                                       \
+        cfg->W = v ? RealShape<T, n>::template type<1>::W : RealShape<T, n>::template type<0>::W;   \
+        cfg->threads = v ? RealShape<T, n>::template type<1>::NT : RealShape<T, n>::template type<0>::NT; \
+        cfg->id = v;                                                                              \
         return 0;
         PFFT_FOR_EACH_NR(PFFT_CASE)
 #undef PFFT_CASE
@@ -189,18 +199,24 @@ static int real_config_t(int NR, KernelConfig *cfg)
     }
 }
 
-template <typename T>
-static hipError_t real_launch_t(int NR, int kind, const StageArgs &a, hipStream_t s)
+template <typename T, int NR, int V>
+static hipError_t real_launch_v(int kind, const StageArgs &a, hipStream_t s)
 {
+    using S = typename RealShape<T, NR>::template type<V>;
     dim3 grid((unsigned)a.ntiles);
+    if (kind == KIND_R2C)
+        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t real_launch_t(int NR, int kind, int variant, const StageArgs &a, hipStream_t s)
+{
     switch (NR) {
-#define PFFT_CASE(n)                                                                   \
-    case n:                                                                            \
-        if (kind == KIND_R2C)                                                          \
-            hipLaunchKernelGGL((k_real<T, n, KIND_R2C>), grid, dim3(C2CDefault<T, n / 2, true>::type::NT), 0, s, a); \
-        else                                                                           \
-            hipLaunchKernelGGL((k_real<T, n, KIND_C2R>), grid, dim3(C2CDefault<T, n / 2, true>::type::NT), 0, s, a); \
-        return hipGetLastError();
+#define PFFT_CASE(n) \
+    case n: return variant == 1 ? real_launch_v<T, n, 1>(kind, a, s) : real_launch_v<T, n, 0>(kind, a, s);
         PFFT_FOR_EACH_NR(PFFT_CASE)
 #undef PFFT_CASE
     default:
@@ -208,15 +224,15 @@ static hipError_t real_launch_t(int NR, int kind, const StageArgs &a, hipStream_
     }
 }
 
-int real_config(int prec, int N, int kind, KernelConfig *cfg)
+int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg)
 {
     (void)kind;
-    return prec == 0 ? real_config_t<float>(N, cfg) : real_config_t<double>(N, cfg);
+    return prec == 0 ? real_config_t<float>(N, variant, cfg) : real_config_t<double>(N, variant, cfg);
 }
 
-hipError_t real_launch(int prec, int N, int kind, const KernelConfig &, const StageArgs &a, hipStream_t s)
+hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s)
 {
-    return prec == 0 ? real_launch_t<float>(N, kind, a, s) : real_launch_t<double>(N, kind, a, s);
+    return prec == 0 ? real_launch_t<float>(N, kind, cfg.id, a, s) : real_launch_t<double>(N, kind, cfg.id, a, s);
 }
 
 }  // namespace pfft

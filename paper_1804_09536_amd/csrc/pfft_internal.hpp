@@ -10,24 +10,35 @@ constexpr int kMaxDims = 8;
 
 // One line tile of a stage: up to W lines that share, on both the source
 // side (0) and the destination side (1), the virtual rank coordinates of every
-// grid direction except the one splitting the transform axis, the local
-// "outer" index O (C-order index over the axes before the transform axis) and
-// the inner extent E (product of local extents after it).  Lines w = 0..count-1
-// differ only by +w in O (contiguous mode: transform axis is the last axis)
-// or by +w in the inner index I (strided mode).
+// grid direction except the one splitting the transform axis and the inner
+// extent E (product of local extents after the transform axis).  O is the
+// local "outer" index (C-order index over the axes before the transform axis)
+// and I the inner index of a line.
 //
-// The element at position j of line w on side s lives at
-//   rank_off[rank + c(j)*R] + ((O + w*dO) * na[c(j)] + loc(j)) * E + I + w*dI
+// The element at position j of a line (O, I) on side s lives at
+//   rank_off[rank + c(j)*R] + (O * na[c(j)] + loc(j)) * E + I
 // where (c(j), loc(j)) = pos[j] names the block along the transform axis and
 // the local index there, na[c] is that block's local extent of the axis and R
 // the rank stride of the grid direction splitting it (0 if whole).
+//
+// Lines w = 0..count-1 of a tile:
+//   run == 0, contiguous mode (transform axis last): (O + w, I);
+//   run == 0, strided mode: (O, I + w);
+//   run > 0 (strided mode only, a tile that continues over consecutive runs
+//   of `run` lines, e.g. where the inner extent is shorter than W): with
+//   q = b0 + w, line w is (O + q / run, I + q % run), i.e. element offset
+//   (q % run) + (q / run) * ostr[s] from line (O, I) of the tile's first run.
 struct Tile {
     int32_t rank[2];
     int32_t count;
-    int32_t flags;  // bit 0: every line pair (2i, 2i+1) starts at an even element on both sides
-    int64_t O[2];
-    int64_t E[2];
-    int64_t I[2];
+    int32_t flags;  // bit 0: every line pair (2i, 2i+1) is two adjacent elements starting at an even one, on both sides
+    int32_t O[2];
+    int32_t E[2];
+    int32_t I[2];
+    int32_t b0;
+    int32_t run;
+    int32_t ostr[2];
+    int32_t reserved[2];
 };
 static_assert(sizeof(Tile) == 64, "Tile must be 64 bytes");
 

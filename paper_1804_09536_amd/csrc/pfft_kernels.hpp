@@ -40,7 +40,7 @@ hipError_t c2c_launch_multi_f64(int N, int contig, int sign, const KernelConfig 
                                 const Tile *tiles, long nt, hipStream_t s);
 int copy_config(int N, KernelConfig *cfg);
 hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
-int real_config(int prec, int N, int kind, KernelConfig *cfg);
+int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg);
 int dft_config(int prec, int N, int kind, KernelConfig *cfg);
 hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
                       hipStream_t s);

@@ -130,6 +130,19 @@ struct Layout {
 
     int64_t total() const { return rank_off[P]; }
 
+    // Global multi-index of the element at buffer offset e.
+    void global_index(int64_t e, int64_t *g) const
+    {
+        const int64_t r = (int64_t)(std::upper_bound(rank_off.begin(), rank_off.end(), e) - rank_off.begin()) - 1;
+        int64_t ls[kMaxDims], st[kMaxDims];
+        block(r, ls, st);
+        int64_t t = e - rank_off[r];
+        for (int m = ndim - 1; m >= 0; m--) {
+            g[m] = st[m] + t % ls[m];
+            t /= ls[m];
+        }
+    }
+
     // Local extent of axis m in a block whose coordinate along m's direction is c.
     int64_t local_extent(int m, int64_t c) const
     {
@@ -274,7 +287,7 @@ struct LineRec {
 // Enumerate every line of a stage along `axis` (source layout A, destination
 // layout B) and group them into tiles of at most W lines that are adjacent in
 // both layouts.
-static void build_tiles(pfft_plan_s *p, Launch &ln, int W)
+static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
 {
     const Layout &A = p->layouts[ln.src];
     const Layout &B = p->layouts[ln.dst];
@@ -334,50 +347,113 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W)
         return x.I[1] < y.I[1];
     };
     std::sort(lines.begin(), lines.end(), less);
+
+    // Runs: maximal sequences of lines that are adjacent on both sides (same
+    // ranks, inner extents and, in strided mode, outer index; consecutive O
+    // (contiguous mode) or I (strided mode)).
+    std::vector<size_t> run_first;
+    for (size_t i = 0; i < lines.size(); i++) {
+        bool cont = i > 0;
+        const LineRec &x = lines[i], &h = lines[i > 0 ? i - 1 : 0];
+        for (int s = 0; s < 2 && cont; s++) {
+            if (x.rank[s] != h.rank[s] || x.E[s] != h.E[s]) cont = false;
+            else if (contig) cont = (x.O[s] == h.O[s] + 1) && (x.I[s] == h.I[s]);
+            else cont = (x.O[s] == h.O[s]) && (x.I[s] == h.I[s] + 1);
+        }
+        if (!cont) run_first.push_back(i);
+    }
+    run_first.push_back(lines.size());
+    const size_t nruns = run_first.size() - 1;
+    auto run_len = [&](size_t r) { return (int64_t)(run_first[r + 1] - run_first[r]); };
+
+    // A strided tile may continue from the end of one run into the next
+    // (line (O + 1, same run start I) on both sides) when every block has the
+    // same local extent of the transform axis on both sides, so that the step
+    // between runs is one number per side.
+    int64_t ostr_na[2] = {0, 0};
+    if (wrap && !contig) {
+        for (int s = 0; s < 2; s++) {
+            const Layout &L = *S[s];
+            const int d = L.axis_dir[a];
+            const int64_t n0 = L.local_extent(a, 0);
+            bool uni = true;
+            if (d >= 0)
+                for (int64_t c = 1; c < L.grid[d]; c++) uni = uni && L.local_extent(a, c) == n0;
+            ostr_na[s] = uni ? n0 : 0;
+        }
+        if (ostr_na[0] == 0 || ostr_na[1] == 0) wrap = false;
+    } else {
+        wrap = false;
+    }
+    auto chains = [&](size_t r) {  // run r + 1 continues run r
+        if (r + 1 >= nruns || run_len(r + 1) != run_len(r)) return false;
+        const LineRec &x = lines[run_first[r]], &y = lines[run_first[r + 1]];
+        for (int s = 0; s < 2; s++)
+            if (x.rank[s] != y.rank[s] || x.E[s] != y.E[s] || y.O[s] != x.O[s] + 1 || y.I[s] != x.I[s]) return false;
+        return true;
+    };
+
     std::vector<Tile> tiles;
-    for (size_t i = 0; i < lines.size();) {
-        const LineRec &h = lines[i];
+    size_t r = 0;
+    int64_t off = 0;  // next line: offset `off` in run r
+    while (r < nruns) {
+        const int64_t len = run_len(r);
         Tile t;
         memset(&t, 0, sizeof t);
+        const LineRec &h = lines[run_first[r] + off];
         for (int s = 0; s < 2; s++) {
             t.rank[s] = h.rank[s];
-            t.O[s] = h.O[s];
-            t.E[s] = h.E[s];
-            t.I[s] = h.I[s];
+            t.O[s] = (int32_t)h.O[s];
+            t.E[s] = (int32_t)h.E[s];
+            t.I[s] = (int32_t)h.I[s];
         }
-        int cnt = 1;
-        size_t k = i + 1;
-        while (k < lines.size() && cnt < W) {
-            const LineRec &x = lines[k];
-            bool ok = true;
-            for (int s = 0; s < 2 && ok; s++) {
-                if (x.rank[s] != h.rank[s] || x.E[s] != h.E[s]) ok = false;
-                else if (contig) ok = (x.O[s] == h.O[s] + cnt) && (x.I[s] == h.I[s]);
-                else ok = (x.O[s] == h.O[s]) && (x.I[s] == h.I[s] + cnt);
+        int64_t cnt = std::min<int64_t>(W, len - off);
+        size_t nr = r;
+        int64_t noff = off + cnt;
+        if (wrap && cnt < W && chains(r)) {
+            // continue over the following runs of the same length
+            const LineRec &r0 = lines[run_first[r]];
+            t.b0 = (int32_t)off;
+            t.run = (int32_t)len;
+            for (int s = 0; s < 2; s++) {
+                t.I[s] = (int32_t)r0.I[s];
+                t.ostr[s] = (int32_t)(ostr_na[s] * r0.E[s]);
             }
-            if (!ok) break;
-            cnt++;
-            k++;
+            while (cnt < W && chains(nr)) {
+                nr++;
+                const int64_t take = std::min<int64_t>(W - cnt, len);
+                cnt += take;
+                noff = take;
+            }
         }
-        t.count = cnt;
-        // flag bit 0: line 0 of the tile sits at an even element at every
-        // position on both sides (so fp32 line pairs move as 16-byte units)
+        t.count = (int32_t)cnt;
+        if (noff == run_len(nr)) {
+            nr++;
+            noff = 0;
+        }
+        r = nr;
+        off = noff;
+        // flag bit 0: in strided mode, every line pair (2i, 2i+1) sits at two
+        // adjacent elements starting at an even one, at every position on
+        // both sides (so fp32 line pairs move as 16-byte units)
         bool even = !contig;
+        if (t.run > 0) even = even && (t.run % 2 == 0) && (t.b0 % 2 == 0) && (t.ostr[0] % 2 == 0) && (t.ostr[1] % 2 == 0);
         for (int s = 0; s < 2 && even; s++) {
             const Layout &L = *S[s];
             const int64_t npos = L.shape[a];
             const int d = L.axis_dir[a];
             const int64_t R = d < 0 ? 0 : L.rstride[d];
+            const int64_t first = t.run > 0 ? t.b0 : 0;  // element offset of line 0 from (O, I)
             for (int64_t j = 0; j < npos && even; j++) {
                 const int64_t c = L.own[a][j], loc = L.loc[a][j];
                 const int64_t na = L.local_extent(a, c);
-                const int64_t addr = L.rank_off[t.rank[s] + c * R] + (t.O[s] * na + loc) * t.E[s] + t.I[s];
+                const int64_t addr =
+                    L.rank_off[t.rank[s] + c * R] + ((int64_t)t.O[s] * na + loc) * t.E[s] + t.I[s] + first;
                 if (addr & 1) even = false;
             }
         }
         t.flags = even ? 1 : 0;
         tiles.push_back(t);
-        i = k;
     }
     ln.ntiles = (int64_t)tiles.size();
     ln.off_tiles = blob_put(p, tiles.data(), tiles.size() * sizeof(Tile));
@@ -397,7 +473,9 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
         return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
     const pfft_tuning &tu = p->tuning;
-    const int variant = ln.kind == KIND_C2C ? (ln.contig ? tu.tile_contig : tu.tile_strided) : 0;
+    const int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R)
+                            ? (ln.contig ? tu.tile_contig : tu.tile_strided)
+                            : 0;
     int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
     if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0)
@@ -411,7 +489,8 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         ln.off_tw = twiddle_table(p, ln.N / 2 > 0 ? ln.N / 2 : 1);
         ln.off_tw2 = twiddle_table(p, ln.N);
     }
-    build_tiles(p, ln, ln.cfg.W);
+    // runs shorter than a tile are chained only for the Stockham stage kernels
+    build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig);
     return PFFT_OK;
 }
 
@@ -786,30 +865,67 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
     const int64_t size[2] = {A.total(), B.total()};
     // positions per side along the axis (real side of R2C/C2R is N real values)
     int64_t npos[2] = {A.shape[ln.axis], B.shape[ln.axis]};
+    // the element read and the element written at one position are the same
+    // global element (C2C and COPY: every axis; R2C/C2R: every other axis)
+    const bool same_pos = npos[0] == npos[1];
     std::vector<uint8_t> hits((size_t)size[1], 0);
     const Tile *tiles = (const Tile *)(p->blob.data() + ln.off_tiles);
     if (ln.ntiles >= ((int64_t)1 << 31)) return fail(PFFT_EINTERNAL, std::string(what) + ": grid too large");
+    const int32_t *pos[2], *na[2];
+    const int64_t *roff[2];
+    for (int s = 0; s < 2; s++) {
+        pos[s] = (const int32_t *)(p->blob.data() + ln.off_pos[s]);
+        na[s] = (const int32_t *)(p->blob.data() + ln.off_na[s]);
+        roff[s] = (const int64_t *)(p->blob.data() + ln.off_rank[s]);
+    }
     for (int64_t ti = 0; ti < ln.ntiles; ti++) {
         const Tile &t = tiles[ti];
         if (t.count < 1 || t.count > ln.cfg.W) return fail(PFFT_EINTERNAL, std::string(what) + ": tile count");
-        for (int s = 0; s < 2; s++) {
-            const Layout &L = *S[s];
-            const int32_t *pos = (const int32_t *)(p->blob.data() + ln.off_pos[s]);
-            const int32_t *na = (const int32_t *)(p->blob.data() + ln.off_na[s]);
-            const int64_t *roff = (const int64_t *)(p->blob.data() + ln.off_rank[s]);
-            for (int w = 0; w < t.count; w++) {
-                for (int64_t j = 0; j < npos[s]; j++) {
-                    int c = pos[2 * j], loc = pos[2 * j + 1];
+        if (t.run < 0 || (t.run > 0 && (ln.contig || t.b0 < 0 || t.b0 >= t.run)))
+            return fail(PFFT_EINTERNAL, std::string(what) + ": tile run");
+        for (int w = 0; w < t.count; w++) {
+            const int64_t jmax = std::max(npos[0], npos[1]);
+            for (int64_t j = 0; j < jmax; j++) {
+                int64_t addr[2] = {-1, -1};
+                for (int s = 0; s < 2; s++) {
+                    if (j >= npos[s]) continue;
+                    const Layout &L = *S[s];
+                    int c = pos[s][2 * j], loc = pos[s][2 * j + 1];
                     int64_t rank = t.rank[s] + (int64_t)c * ln.R[s];
                     if (rank < 0 || rank >= L.P) return fail(PFFT_EINTERNAL, std::string(what) + ": rank");
-                    int64_t O = t.O[s] + (ln.contig ? w : 0), I = t.I[s] + (ln.contig ? 0 : w);
-                    int64_t addr = roff[rank] + (O * na[c] + loc) * t.E[s] + I;
-                    if (addr < roff[rank] || addr >= roff[rank + 1] || addr >= size[s])
+                    int64_t O = t.O[s], I = t.I[s];
+                    if (t.run > 0) {
+                        const int64_t q = t.b0 + w;
+                        O += q / t.run;
+                        I += q % t.run;
+                        // the kernels step between runs by ostr elements
+                        const int64_t a0 = roff[s][rank] + ((int64_t)t.O[s] * na[s][c] + loc) * t.E[s] + t.I[s];
+                        const int64_t a1 = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
+                        if (a1 - a0 != (q % t.run) + (q / t.run) * (int64_t)t.ostr[s])
+                            return fail(PFFT_EINTERNAL, std::string(what) + ": run stride");
+                    } else if (ln.contig) {
+                        O += w;
+                    } else {
+                        I += w;
+                    }
+                    addr[s] = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
+                    if (I < 0 || I >= t.E[s] || addr[s] < roff[s][rank] || addr[s] >= roff[s][rank + 1] ||
+                        addr[s] >= size[s])
                         return fail(PFFT_EINTERNAL, std::string(what) + ": address out of its block");
                     if (s == 1) {
-                        if (hits[addr] == 255) return fail(PFFT_EINTERNAL, std::string(what) + ": overflow");
-                        hits[addr]++;
+                        if (hits[addr[s]] == 255) return fail(PFFT_EINTERNAL, std::string(what) + ": overflow");
+                        hits[addr[s]]++;
                     }
+                }
+                if (j < npos[0] && j < npos[1]) {
+                    int64_t g0[kMaxDims], g1[kMaxDims];
+                    A.global_index(addr[0], g0);
+                    B.global_index(addr[1], g1);
+                    for (int m = 0; m < A.ndim; m++)
+                        if ((m != ln.axis || same_pos) && g0[m] != g1[m])
+                            return fail(PFFT_EINTERNAL, std::string(what) + ": source and destination differ");
+                    if (g0[ln.axis] != j && same_pos)
+                        return fail(PFFT_EINTERNAL, std::string(what) + ": position");
                 }
             }
         }
