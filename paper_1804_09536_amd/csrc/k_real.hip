@@ -112,26 +112,44 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a)
         SideAddr<P> cs;
         cs.init(a.side[0], t, 0, jt, TPL, M + 1, true);
         const bool half = (a.flags & SF_HALVE_INTERIOR) != 0;
+        // all loads first (a full tile without predicates), then the LDS
+        // writes, so the loads are in flight together
+        if (count == W) {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++) v[l][m] = in[cs.off[m] + wl[l] * cs.stride[m]];
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++)
+                    v[l][m] = valid[l] ? in[cs.off[m] + wl[l] * cs.stride[m]] : c_zero<T2>();
+        }
+        T2 xm[NL];
+        if (jt == 0) {
+            const Side &sd = a.side[0];
+            const int2 pc = sd.pos[M];
+            const long na = sd.na[pc.x];
+            const long base = sd.rank_off[t.rank[0] + pc.x * sd.R];
+#pragma unroll
+            for (int l = 0; l < NL; l++) {
+                const long addr = base + ((long)(t.O[0] + wl[l]) * na + pc.y) * t.E[0] + t.I[0];
+                xm[l] = valid[l] ? in[addr] : c_zero<T2>();
+            }
+        }
 #pragma unroll
         for (int l = 0; l < NL; l++) {
 #pragma unroll
             for (int m = 0; m < P; m++) {
                 const int k = jt + m * TPL;
-                T2 x = valid[l] ? in[cs.off[m] + wl[l] * cs.stride[m]] : c_zero<T2>();
+                T2 x = v[l][m];
                 if (k == 0) x.y = (T)0;
                 if (half && k > 0) x = c_scale(x, (T)0.5);
                 lds[RL::idx(wl[l], k)] = x;
             }
             if (jt == 0) {
-                T2 x = c_zero<T2>();
-                if (valid[l]) {
-                    const Side &sd = a.side[0];
-                    const int2 pc = sd.pos[M];
-                    const long na = sd.na[pc.x];
-                    const long base = sd.rank_off[t.rank[0] + pc.x * sd.R];
-                    const long addr = base + ((long)(t.O[0] + wl[l]) * na + pc.y) * t.E[0] + t.I[0];
-                    x = in[addr];
-                }
+                T2 x = xm[l];
                 x.y = (T)0;
                 lds[RL::idx(wl[l], M)] = x;
             }
