@@ -86,6 +86,12 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_PLACE_BWD_MASK (3u << 5)
 #define PFFT_LAYOUTS_ONLY 4u      /* plan layouts and redistributions only: no transform kernels are
                                      set up (any lengths), pfft_forward & co. return PFFT_EUNSUPPORTED */
+/* The transforms may overwrite a complex input buffer and use it for intermediate results (the
+   two-largest-buffers scheme of Sec. 3.5): a c2c plan then needs no workspace at all when its
+   chain has an odd number of partial transforms or its first partial transform stays in its own
+   layout (it then runs in place), an R2C plan one spectrum-sized buffer instead of two.  `in` and
+   `out` must not overlap.  A real input is never written. */
+#define PFFT_DESTROY_INPUT (1u << 8)
 
 /* status codes */
 #define PFFT_OK 0
@@ -115,7 +121,7 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *   nsteps: number of chain steps (ignored when chain is NULL).
  *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
  *     or-ed with one forward and one backward placement (PFFT_PLACE_*,
- *     PFFT_PLACE_BWD_*) and with PFFT_LAYOUTS_ONLY.
+ *     PFFT_PLACE_BWD_*), PFFT_DESTROY_INPUT and PFFT_LAYOUTS_ONLY.
  * The chain must leave every axis transformed (each axis whole in some
  * layout).  For PFFT_R2C the last axis must be whole in layout 0.
  * Returns PFFT_OK and *out, or an error (then *out is NULL).
@@ -180,7 +186,8 @@ int pfft_device_state_bytes(pfft_plan plan, size_t *bytes);
  */
 int pfft_bind_device_state(pfft_plan plan, void *dev, hipStream_t stream);
 
-/* Workspace bytes needed by pfft_forward/backward/adjoint_* (256-aligned). */
+/* Workspace bytes needed by pfft_forward/backward/adjoint_* (256-aligned;
+   0 when the transforms need none: `work` may then be NULL). */
 int pfft_workspace_bytes(pfft_plan plan, size_t *bytes);
 
 /*
@@ -195,6 +202,7 @@ int pfft_redistribute(pfft_plan plan, int layout_from, int layout_to, const void
 /*
  * Forward transform: `in` in layout 0 (real for R2C), `out` in the last
  * layout (half spectrum for R2C).  `work`: pfft_workspace_bytes bytes.
+ * `in` is left unchanged unless the plan has PFFT_DESTROY_INPUT.
  */
 int pfft_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
 

@@ -19,6 +19,7 @@ NORMS = {"forward": 0, "backward": 1, "none": 2}
 PATHS = {"fused": 0, "unfused": 1, "pack_realign": 2}
 PFFT_LAYOUTS_ONLY = 4
 PFFT_PLACE_SCATTER = 8
+PFFT_DESTROY_INPUT = 1 << 8
 PLACEMENTS = {"gather": 0, "scatter": 1, "direct": 2, "final": 3}
 
 _lib = None

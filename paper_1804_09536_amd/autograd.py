@@ -36,14 +36,21 @@ class _Backward(torch.autograd.Function):
         return ctx.plan.adjoint_backward(g.contiguous()), None
 
 
+def _check(plan: Plan):
+    if plan.destroy_input:
+        raise ValueError("autograd needs a plan that leaves its inputs intact (destroy_input=False)")
+
+
 def forward(x: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Distributed forward FFT of the rank-blocked buffer x (input layout),
     differentiable."""
+    _check(plan)
     return _Forward.apply(x, plan)
 
 
 def backward(x: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Distributed backward FFT (output layout -> input layout), differentiable."""
+    _check(plan)
     return _Backward.apply(x, plan)
 
 

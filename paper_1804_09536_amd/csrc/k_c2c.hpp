@@ -255,9 +255,12 @@ struct TwiddleStage {
     }
 };
 
+// `tiles` is a.tiles passed as a restrict-qualified argument: tile records
+// are then known to be unchanged by the kernel's stores and can be read
+// through the scalar cache.
 template <typename T, int N, bool CONTIG, int SIGN, class S>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c(
-    StageArgs a)
+    StageArgs a, const Tile *__restrict__ tiles)
 {
     using Wk = C2CWorker<T, N, CONTIG, SIGN, S>;
     using T2 = typename Wk::T2;
@@ -273,7 +276,9 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     int c;
     for (long ti = blockIdx.x; ti < nt; ti += G) {
         wk.refresh();
-        const Tile &t = a.tiles[ti];
+        // (contiguous stages measured faster with the tile read through the
+        // vector path)
+        const Tile &t = CONTIG ? a.tiles[ti] : tiles[ti];
         wk.load(a, t, v, d, c);
         wk.process(a, t, v, d, c, lds, tw);
     }

@@ -52,7 +52,7 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
         if (g > resident) g = resident;
     }
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a);
+    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ __device__ __forceinline__ long dft_addr(const Side &sd, const Tile &t, int s, i
 // bins.  KIND_C2R: N/2+1 bins (Hermitian extension, imaginary parts of bins
 // 0 and N/2 ignored) -> N real points.
 template <typename T, int KIND>
-__global__ __launch_bounds__(kDftThreads) void k_dft(StageArgs a, int sign, int contig, int W)
+__global__ __launch_bounds__(kDftThreads) void k_dft(StageArgs a, const Tile *__restrict__ tiles, int sign, int contig,
+                                                     int W)
 {
     using T2 = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(kDftThreads) void k_dft(StageArgs a, int sign, int 
     const int nout = KIND == KIND_R2C ? H : N;   // positions written per line
     T2 *tw = (T2 *)smem;                         // N twiddles e^{sign 2 pi i m / N}
     T2 *line = tw + N;                           // W lines of nin complex values
-    const Tile &t = a.tiles[blockIdx.x];
+    const Tile &t = tiles[blockIdx.x];
     const int count = t.count;
     const T2 *tab = (const T2 *)(KIND == KIND_C2C ? a.twiddle : a.twiddle2);  // N-point table
     for (int i = threadIdx.x; i < N; i += kDftThreads) {
@@ -138,7 +139,7 @@ hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const Ker
     const size_t lds = dft_lds(prec, N, cfg.W, kind);
     if (lds > 64 * 1024 && dft_prepare() != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.ntiles), block(kDftThreads);
-#define PFFT_DFT(T, K) hipLaunchKernelGGL((k_dft<T, K>), grid, block, lds, s, a, sign, contig, cfg.W)
+#define PFFT_DFT(T, K) hipLaunchKernelGGL((k_dft<T, K>), grid, block, lds, s, a, a.tiles, sign, contig, cfg.W)
     if (prec == 0) {
         if (kind == KIND_C2C) PFFT_DFT(float, KIND_C2C);
         else if (kind == KIND_R2C) PFFT_DFT(float, KIND_R2C);

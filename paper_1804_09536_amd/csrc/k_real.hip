@@ -25,7 +25,7 @@ struct RealLds {
 
 // S: the launch shape of the M-point transform (a contiguous-mode C2CCfg).
 template <typename T, int NR, int KIND, class S>
-__global__ __launch_bounds__(S::NT) void k_real(StageArgs a)
+__global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restrict__ tiles)
 {
     using T2 = typename V2<T>::type;
     constexpr int M = NR / 2;
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a)
     constexpr int LDS_N = (LT::SIZE > W * RL::LINE) ? LT::SIZE : W * RL::LINE;
     __shared__ T2 lds[LDS_N];
 
-    const Tile &t = a.tiles[blockIdx.x];
+    const Tile &t = tiles[blockIdx.x];
     const int count = t.count;
     const int tid = threadIdx.x;
     const int jt = tid % TPL;
@@ -223,9 +223,9 @@ static hipError_t real_launch_v(int kind, const StageArgs &a, hipStream_t s)
     using S = typename RealShape<T, NR>::template type<V>;
     dim3 grid((unsigned)a.ntiles);
     if (kind == KIND_R2C)
-        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, a);
+        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, a, a.tiles);
     else
-        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, a);
+        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 

@@ -806,29 +806,66 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
 // mode 0: forward factors from norm on forward, 1: backward factors.
 // Source and destination buffer of every launch of a list that reads `in`
 // and must end in `out`, ping-ponging through the workspace.
-static void assign_buffers(const pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out,
-                           void *work, std::vector<const void *> &srcs, std::vector<void *> &dsts)
+// Buffers of a launch list: launch k reads srcs[k] and writes dsts[k]; the
+// last one writes `out`.  Intermediates ping-pong between `out` and one
+// workspace buffer (two when `out` is real), or, with PFFT_DESTROY_INPUT and a
+// complex input, between `out` and `in` (the first launch runs in place on
+// `in` when it keeps its own layout, else it writes the workspace once).
+// Returns the number of workspace buffers used.
+static int assign_buffers(const pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out,
+                          void *work, std::vector<const void *> &srcs, std::vector<void *> &dsts)
 {
     const int n = (int)list.size();
     uint8_t *w0 = (uint8_t *)work;
     uint8_t *w1 = w0 ? w0 + ((p->spec_bytes + 255) & ~(size_t)255) : nullptr;
     const bool out_is_real = n > 0 && list.back().dst == p->real0;
+    const bool in_is_real = n > 0 && list[0].src == p->real0;
+    const bool destroy = (p->flags & PFFT_DESTROY_INPUT) != 0 && !in_is_real;
+    void *in_w = const_cast<void *>(in);
     const void *cur = in;
-    int parity = 0;
+    int used = 0;
     srcs.assign(n, nullptr);
     dsts.assign(n, nullptr);
     for (int k = 0; k < n; k++) {
         void *dst;
-        if (k == n - 1)
+        if (k == n - 1) {
             dst = out;
-        else if (out_is_real)
-            dst = (parity++ % 2 == 0) ? (void *)w0 : (void *)w1;
-        else
-            dst = ((n - 1 - k) % 2 == 0) ? out : (void *)w0;
+        } else if (out_is_real) {
+            if (destroy)
+                dst = (k % 2 == 0) ? (void *)w0 : in_w;
+            else
+                dst = (k % 2 == 0) ? (void *)w0 : (void *)w1;
+        } else if ((n - 1 - k) % 2 == 0) {
+            dst = out;
+        } else if (destroy) {
+            // only the first launch can land on `in`; in place if it keeps its layout
+            const bool in_place = list[0].src == list[0].dst && list[0].kind == KIND_C2C;
+            dst = (k > 0 || in_place) ? in_w : (void *)w0;
+        } else {
+            dst = w0;
+        }
+        if (dst == (void *)w0) used = std::max(used, 1);
+        if (dst == (void *)w1) used = 2;
         srcs[k] = cur;
         dsts[k] = dst;
         cur = dst;
     }
+    return used;
+}
+
+// Workspace buffers (of the spectrum's size) the plan's lists need.
+static int work_buffers(const pfft_plan_s *p)
+{
+    static uint8_t probe[3];  // distinct stand-in addresses for in, out, work
+    std::vector<const void *> srcs;
+    std::vector<void *> dsts;
+    int used = 0;
+    for (const std::vector<Launch> *list : {&p->fwd, &p->bwd}) {
+        // the backward and the adjoints run these lists too; which one is
+        // `in` only decides whether the input is real
+        used = std::max(used, assign_buffers(p, *list, probe, probe + 1, probe + 2, srcs, dsts));
+    }
+    return used;
 }
 
 static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out, void *work,
@@ -838,10 +875,9 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
     if (!p->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     if (!in || !out) return fail(PFFT_EINVAL, "null buffer");
     const int n = (int)list.size();
-    if (n > 1 && !work) return fail(PFFT_EINVAL, "null workspace");
     std::vector<const void *> srcs;
     std::vector<void *> dsts;
-    assign_buffers(p, list, in, out, work, srcs, dsts);
+    if (assign_buffers(p, list, in, out, work, srcs, dsts) > 0 && !work) return fail(PFFT_EINVAL, "null workspace");
     for (int k = 0; k < n; k++) {
         const Launch &ln = list[k];
         double scale = (ln.kind == KIND_COPY) ? 1.0 : axis_scale(p, ln.scale_axis, forward_factors);
@@ -996,7 +1032,7 @@ static int batch_plan(pfft_batch_s *b)
         // the backward writes the input layout, so both buffers hold either
         b->in_bytes += align256(std::max(ib, ob));
         b->out_bytes += align256(std::max(ib, ob));
-        b->work_bytes += align256(p->spec_bytes) * (p->kind == PFFT_R2C ? 2 : 1);
+        b->work_bytes += align256(p->spec_bytes) * (size_t)work_buffers(p);
         // members that are the same plan share one copy of its tables
         size_t off = SIZE_MAX;
         for (int q = 0; q < m; q++)
@@ -1128,7 +1164,8 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
     if (kind != PFFT_C2C && kind != PFFT_R2C) return fail(PFFT_EDTYPE, "bad kind");
     if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
-    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK)) != 0 ||
+    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK | PFFT_DESTROY_INPUT)) !=
+            0 ||
         (flags & PFFT_PATH_MASK) == 3u)
         return fail(PFFT_EINVAL, "bad flags");
     if (chain && nsteps < 0) return fail(PFFT_EINVAL, "bad nsteps");
@@ -1304,7 +1341,7 @@ int pfft_workspace_bytes(pfft_plan plan, size_t *bytes)
 {
     if (!plan || !bytes) return fail(PFFT_EINVAL, "null argument");
     size_t one = (plan->spec_bytes + 255) & ~(size_t)255;
-    *bytes = plan->kind == PFFT_R2C ? 2 * one : one;
+    *bytes = one * (size_t)work_buffers(plan);
     return PFFT_OK;
 }
 

@@ -95,3 +95,22 @@ def test_calls_before_binding_fail_cleanly():
     assert lib.pfft_forward(None, None, None, None, None) == -1
     assert lib.pfft_redistribute(p._h, 0, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -6
     assert _lib.strerror(-5) == "unsupported transform length"
+
+
+@pytest.mark.parametrize("shape,grid,kind,placement,path,plain,destroyed", [
+    ((64, 32, 16), (4, 4), "c2c", None, "fused", 1, 0),                          # 3 transforms: odd
+    ((8, 8, 8, 8), (2, 2, 2), "c2c", None, "fused", 1, 0),                       # 4: the first runs in place
+    ((8, 8, 8, 8), (2, 2, 2), "c2c", ("scatter", "gather"), "fused", 1, 1),      # first one leaves its layout
+    ((16, 16, 16), (2, 2), "r2c", None, "fused", 2, 1),
+    ((16, 16, 16), (2, 2), "c2c", None, "unfused", 1, 0),
+    ((16, 16, 16), (2, 2), "c2c", None, "pack_realign", 1, 0),
+])
+def test_destroy_input_workspace(shape, grid, kind, placement, path, plain, destroyed):
+    # the two-largest-buffers scheme: intermediates reuse a complex input
+    from paper_1804_09536_amd.plan import Plan
+    a = Plan(shape, grid, kind=kind, placement=placement, path=path)
+    b = Plan(shape, grid, kind=kind, placement=placement, path=path, destroy_input=True)
+    one = (a.buffer_numel(a.num_layouts - 1) * 8 + 255) // 256 * 256
+    assert a.workspace_bytes() == plain * one
+    assert b.workspace_bytes() == destroyed * one
+    b.validate()

@@ -155,3 +155,33 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
             assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs)
             back = _host(p.backward(_to_dev(ref)))
             assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs)
+
+
+@pytest.mark.parametrize("shape,grid,kind,placement,path", [
+    ((64, 32, 16), (4, 4), "c2c", None, "fused"),
+    ((8, 12, 8, 16), (2, 3, 2), "c2c", None, "fused"),
+    ((8, 12, 8, 16), (2, 3, 2), "c2c", ("scatter", "gather"), "fused"),
+    ((24, 16, 32), (2, 4), "r2c", None, "fused"),
+    ((16, 24, 16), (2, 3), "c2c", None, "pack_realign"),
+])
+def test_destroy_input_gives_identical_results(shape, grid, kind, placement, path):
+    # intermediates on the input buffer (and a first partial transform in
+    # place) change no arithmetic: results equal the input-preserving plan's
+    print("case", shape, grid, kind, placement, path, flush=True)
+    keep = Plan(shape, grid, kind=kind, placement=placement, path=path)
+    dest = Plan(shape, grid, kind=kind, placement=placement, path=path, destroy_input=True)
+    n = keep.buffer_numel(0, real=(kind == "r2c"))
+    u = (inputs.uniform_complex(n, [9], np.complex64) if kind == "c2c"
+         else inputs.gaussian_real(n, [9], np.float32))
+    ref = _host(keep.forward(_to_dev(u)))
+    ref_b = _host(keep.backward(_to_dev(ref)))
+    x = _to_dev(u)
+    got = _host(dest.forward(x))
+    assert got.tobytes() == ref.tobytes()
+    if kind == "r2c":
+        assert _host(x).tobytes() == u.tobytes()   # a real input is never written
+    y = _to_dev(ref)
+    back = _host(dest.backward(y))
+    assert back.tobytes() == ref_b.tobytes()
+    if dest.workspace_bytes() == 0:
+        assert dest.workspace() is None
