@@ -28,6 +28,12 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X published peak
 WORKLOADS = {
     # name: (shape, grid, kind, precision, chain)
     "pencil512": ((512, 512, 512), (8, 8), "c2c", "f32", None),
+    # the same array over other virtual grids: slab, coarser and finer pencils,
+    # and the thin-slab limit (one plane per rank)
+    "slab512": ((512, 512, 512), (8,), "c2c", "f32", None),
+    "pencil512_4x4": ((512, 512, 512), (4, 4), "c2c", "f32", None),
+    "pencil512_32x16": ((512, 512, 512), (32, 16), "c2c", "f32", None),
+    "slab512_thin": ((512, 512, 512), (512,), "c2c", "f32", None),
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
     "r2c512": ((512, 512, 512), (8, 8), "r2c", "f32", None),

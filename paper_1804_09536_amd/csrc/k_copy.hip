@@ -14,9 +14,9 @@ constexpr int kCopyUnroll = 8;
 // One workgroup per tile of lines; TPL threads per line slot (a power of two
 // <= 64), positions j = jt + u*TPL in chunks of kCopyUnroll per thread.
 template <typename E>
-__global__ __launch_bounds__(kCopyThreads) void k_copy(StageArgs a, const Tile *__restrict__ tiles, int TPL)
+__global__ __launch_bounds__(kCopyThreads) void k_copy(StageArgs a, int TPL)
 {
-    const Tile &t = tiles[blockIdx.x];
+    const Tile &t = a.tiles[blockIdx.x];
     const int count = t.count;
     const int N = a.N;
     const int jt = threadIdx.x % TPL;
@@ -73,9 +73,9 @@ hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a
 {
     dim3 grid((unsigned)a.ntiles), block(kCopyThreads);
     switch (esize) {
-    case 4: hipLaunchKernelGGL((k_copy<float>), grid, block, 0, s, a, a.tiles, cfg.id); break;
-    case 8: hipLaunchKernelGGL((k_copy<float2>), grid, block, 0, s, a, a.tiles, cfg.id); break;
-    case 16: hipLaunchKernelGGL((k_copy<double2>), grid, block, 0, s, a, a.tiles, cfg.id); break;
+    case 4: hipLaunchKernelGGL((k_copy<float>), grid, block, 0, s, a, cfg.id); break;
+    case 8: hipLaunchKernelGGL((k_copy<float2>), grid, block, 0, s, a, cfg.id); break;
+    case 16: hipLaunchKernelGGL((k_copy<double2>), grid, block, 0, s, a, cfg.id); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
