@@ -14,8 +14,14 @@ Citations name the paper's sections and equations:
   * Sec. 3.4 (Eqs. pencil0-pencil2) and Sec. 3.5 (Eqs. 4d_fft0-4d_fft3): the
     chain of alignments for a grid of dimension g on a d-dim array.
 
+  * Real-to-real transforms (the "similar" transforms the method also carries,
+    Sec. 1 and the conclusions): per axis the quarter-wave cosine or sine
+    transform of type II and its inverse of type III, in the unnormalised
+    form Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2N) (type II cosine) and the
+    standard companions; a forward factor 1/(2N) makes type III undo type II.
+
 Data model: one numpy buffer per alignment holding the rank blocks (C order)
-one after another in rank order; complex data is complex128.
+one after another in rank order; complex data is complex128, real float64.
 """
 from __future__ import annotations
 
@@ -37,6 +43,7 @@ __all__ = [
     "redistribute_pairs", "fft_axis", "dft1", "bruteforce_dftn", "forward",
     "backward", "adjoint_forward", "adjoint_backward", "wavenumber_weight",
     "loss_and_grad", "Chain", "dft_bins", "layout_offset",
+    "R2R_KINDS", "r2r_matrix", "r2r_axis", "bruteforce_r2rn",
 ]
 
 
@@ -342,6 +349,81 @@ def _c2r_last(buf, lay_real: Layout, scale, halve_interior=False):
     return out
 
 
+# ------------------------------------------------- real-to-real (r2r) --
+
+R2R_KINDS = ("dct2", "dst2")
+
+
+def r2r_matrix(n: int, kind: str, inverse: bool) -> np.ndarray:
+    """Matrix (row k = output, column j = input) of one line's unnormalised
+    real-to-real transform, from the definitions:
+      dct2: Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2n)
+      dct3 (inverse of dct2): Y_k = x_0 + 2 sum_{j>=1} x_j cos(pi j (2k+1) / 2n)
+      dst2: Y_k = 2 sum_j x_j sin(pi (2j+1) (k+1) / 2n)
+      dst3 (inverse of dst2): Y_k = (-1)^k x_{n-1} + 2 sum_{j<n-1} x_j sin(pi (j+1) (2k+1) / 2n)
+    Angles are reduced exactly as integers m/(4n) of a full turn before the
+    FP64 cos/sin; type III followed by type II gives 2n times the identity."""
+    if kind not in R2R_KINDS:
+        raise ValueError("kind must be one of %s" % (R2R_KINDS,))
+    j = np.arange(n, dtype=np.int64)[None, :]
+    k = np.arange(n, dtype=np.int64)[:, None]
+    turn = 4 * n
+    if kind == "dct2" and not inverse:
+        m = ((2 * j + 1) * k) % turn
+        return 2.0 * np.cos(2.0 * np.pi * m / turn)
+    if kind == "dct2":
+        m = (j * (2 * k + 1)) % turn
+        M = 2.0 * np.cos(2.0 * np.pi * m / turn)
+        M[:, 0] = 1.0
+        return M
+    if not inverse:
+        m = ((2 * j + 1) * (k + 1)) % turn
+        return 2.0 * np.sin(2.0 * np.pi * m / turn)
+    m = ((j + 1) * (2 * k + 1)) % turn
+    M = 2.0 * np.sin(2.0 * np.pi * m / turn)
+    M[:, n - 1] = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return M
+
+
+def r2r_axis(buf: np.ndarray, lay: Layout, axis: int, kind: str, inverse: bool, scale: float) -> np.ndarray:
+    """Real-to-real partial transform along ``axis`` of every line of every
+    rank block (the axis must be whole in ``lay``): the line matrix applied
+    along the axis (a matrix product), times ``scale``."""
+    if lay.axis_dir[axis] != -1:
+        raise ValueError("axis %d is distributed in this layout" % axis)
+    M = r2r_matrix(lay.shape[axis], kind, inverse)
+    x = np.ascontiguousarray(buf, dtype=np.float64)
+    out = np.empty_like(x)
+    offs = lay.offsets()
+    for r in range(lay.nranks):
+        ls, _ = lay.block(r)
+        if offs[r + 1] == offs[r]:
+            continue
+        blk = x[offs[r]:offs[r + 1]].reshape(ls)
+        y = np.moveaxis(np.tensordot(M, blk, axes=([1], [axis])), 0, axis)
+        out[offs[r]:offs[r + 1]] = (y * scale).reshape(-1)
+    return out
+
+
+def bruteforce_r2rn(glob: np.ndarray, kinds, inverse: bool, scales) -> np.ndarray:
+    """The separable multi-dimensional real-to-real transform evaluated term
+    by term on a (tiny) global array: every output element is the full sum
+    over every input element of the product of the per-axis coefficients."""
+    import itertools
+    x = np.asarray(glob, dtype=np.float64)
+    mats = [r2r_matrix(n, kd, inverse) * sc for n, kd, sc in zip(x.shape, kinds, scales)]
+    out = np.zeros_like(x)
+    for kidx in itertools.product(*[range(n) for n in x.shape]):
+        acc = 0.0
+        for jidx in itertools.product(*[range(n) for n in x.shape]):
+            c = 1.0
+            for a in range(x.ndim):
+                c *= mats[a][kidx[a], jidx[a]]
+            acc += c * x[jidx]
+        out[kidx] = acc
+    return out
+
+
 # ---------------------------------------------------------------- chains --
 
 
@@ -358,14 +440,19 @@ class Chain:
     dirs: list
     kind: str = "c2c"
     norm: str = "forward"
+    r2r: tuple = None  # kind="r2r": the forward transform of each axis (R2R_KINDS)
 
     @staticmethod
-    def paper(shape, grid, kind="c2c", norm="forward", steps=None):
+    def paper(shape, grid, kind="c2c", norm="forward", steps=None, r2r=None):
         shape = tuple(int(x) for x in shape)
         grid = tuple(int(x) for x in grid)
         dirs = (paper_layouts(len(shape), len(grid)) if steps is None
                 else layouts_from_steps(len(shape), len(grid), steps))
-        return Chain(shape, grid, dirs, kind, norm)
+        if kind == "r2r":
+            r2r = tuple(r2r) if r2r is not None else ("dct2",) * len(shape)
+            if len(r2r) != len(shape) or any(k not in R2R_KINDS for k in r2r):
+                raise ValueError("one r2r kind per axis")
+        return Chain(shape, grid, dirs, kind, norm, r2r)
 
     def spectral_shape(self):
         if self.kind == "r2c":
@@ -377,13 +464,14 @@ class Chain:
         return Layout(shp, self.grid, tuple(self.dirs[li]))
 
     def input_layout(self) -> Layout:
-        return self.layout(0, spectral=(self.kind == "c2c"))
+        return self.layout(0, spectral=(self.kind != "r2c"))
 
     def output_layout(self) -> Layout:
         return self.layout(len(self.dirs) - 1)
 
     def scale(self, axis: int, direction: str) -> float:
-        n = self.shape[axis]
+        # real-to-real: type III undoes type II up to 2N
+        n = self.shape[axis] * (2 if self.kind == "r2r" else 1)
         if self.norm == "forward":
             return 1.0 / n if direction == "forward" else 1.0
         if self.norm == "backward":
@@ -403,7 +491,9 @@ def _run_forward(ch: Chain, buf, sign, scale_of, r2c_mode):
         while cur < li:
             data = redistribute(data, ch.layout(cur), ch.layout(cur + 1))
             cur += 1
-        if first and ch.kind == "r2c":
+        if ch.kind == "r2r":
+            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], False, scale_of(axis))
+        elif first and ch.kind == "r2c":
             assert axis == len(ch.shape) - 1, "r2c needs the last axis transformed first"
             data = _r2c_last(data, ch.layout(0, spectral=False), scale_of(axis))
             if r2c_mode == "r2c_double":
@@ -430,7 +520,9 @@ def _run_backward(ch: Chain, buf, sign, scale_of, halve):
             data = redistribute(data, ch.layout(cur), ch.layout(cur - 1))
             cur -= 1
         last = idx == len(sched) - 1
-        if last and ch.kind == "r2c":
+        if ch.kind == "r2r":
+            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], True, scale_of(axis))
+        elif last and ch.kind == "r2c":
             data = _c2r_last(data, ch.layout(0, spectral=False), scale_of(axis), halve_interior=halve)
         else:
             data = fft_axis(data, ch.layout(li), axis, sign, scale_of(axis))
