@@ -385,13 +385,16 @@ def r2r_matrix(n: int, kind: str, inverse: bool) -> np.ndarray:
     return M
 
 
-def r2r_axis(buf: np.ndarray, lay: Layout, axis: int, kind: str, inverse: bool, scale: float) -> np.ndarray:
+def r2r_axis(buf: np.ndarray, lay: Layout, axis: int, kind: str, inverse: bool, scale: float,
+             transpose: bool = False) -> np.ndarray:
     """Real-to-real partial transform along ``axis`` of every line of every
-    rank block (the axis must be whole in ``lay``): the line matrix applied
-    along the axis (a matrix product), times ``scale``."""
+    rank block (the axis must be whole in ``lay``): the line matrix (or its
+    transpose) applied along the axis (a matrix product), times ``scale``."""
     if lay.axis_dir[axis] != -1:
         raise ValueError("axis %d is distributed in this layout" % axis)
     M = r2r_matrix(lay.shape[axis], kind, inverse)
+    if transpose:
+        M = M.T
     x = np.ascontiguousarray(buf, dtype=np.float64)
     out = np.empty_like(x)
     offs = lay.offsets()
@@ -492,7 +495,9 @@ def _run_forward(ch: Chain, buf, sign, scale_of, r2c_mode):
             data = redistribute(data, ch.layout(cur), ch.layout(cur + 1))
             cur += 1
         if ch.kind == "r2r":
-            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], False, scale_of(axis))
+            # the adjoint of the backward walks this chain with the inverse's transpose
+            adj = r2c_mode == "r2c_double"
+            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], adj, scale_of(axis), transpose=adj)
         elif first and ch.kind == "r2c":
             assert axis == len(ch.shape) - 1, "r2c needs the last axis transformed first"
             data = _r2c_last(data, ch.layout(0, spectral=False), scale_of(axis))
@@ -521,7 +526,8 @@ def _run_backward(ch: Chain, buf, sign, scale_of, halve):
             cur -= 1
         last = idx == len(sched) - 1
         if ch.kind == "r2r":
-            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], True, scale_of(axis))
+            # the adjoint of the forward walks this chain with the forward's transpose
+            data = r2r_axis(data, ch.layout(li), axis, ch.r2r[axis], not halve, scale_of(axis), transpose=halve)
         elif last and ch.kind == "r2c":
             data = _c2r_last(data, ch.layout(0, spectral=False), scale_of(axis), halve_interior=halve)
         else:

@@ -86,3 +86,31 @@ def test_round_trip(norm):
     back = oracle.backward(ch, oracle.forward(ch, x))
     f = 1.0 if norm != "none" else float(np.prod([2 * n for n in shape]))
     assert np.abs(back - f * x).max() < 1e-11 * f
+
+
+@pytest.mark.parametrize("kinds", [("dct2", "dst2", "dct2"), ("dst2", "dst2", "dst2")])
+@pytest.mark.parametrize("norm", ["forward", "backward"])
+def test_adjoints_satisfy_dot_product_identity(kinds, norm):
+    # <F x, y> = <x, F^T y> and <B y, x> = <y, B^T x> in FP64
+    shape, grid = (6, 8, 10), (2, 3)
+    ch = oracle.Chain.paper(shape, grid, kind="r2r", norm=norm, r2r=kinds)
+    rng = np.random.default_rng(11)
+    n = int(np.prod(shape))
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    lhs = np.dot(oracle.forward(ch, x), y)
+    rhs = np.dot(x, oracle.adjoint_forward(ch, y))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+    lhs = np.dot(oracle.backward(ch, y), x)
+    rhs = np.dot(y, oracle.adjoint_backward(ch, x))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_adjoint_is_the_inverse_with_the_special_element_reweighted():
+    # type II transposed = type III with its special input doubled (cosine: first, sine: last)
+    n = 9
+    for kind, sp in (("dct2", 0), ("dst2", n - 1)):
+        F = oracle.r2r_matrix(n, kind, False)
+        B = oracle.r2r_matrix(n, kind, True)
+        D = np.eye(n)
+        D[sp, sp] = 2.0
+        assert np.abs(F.T - B @ D).max() < 1e-12 * n
