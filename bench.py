@@ -37,10 +37,13 @@ WORKLOADS = {
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
     "r2c512": ((512, 512, 512), (8, 8), "r2c", "f32", None),
+    # real-to-real: type II cosine transform on every axis (type III back)
+    "dct512": ((512, 512, 512), (8, 8), "r2r", "f32", None),
     "c2c4d64": ((64, 64, 64, 64), (2, 2, 4), "c2c", "f32", None),
 }
 
-KIND_NAMES = {"c2c": "c2c_stage", "copy": "redistribute_copy", "r2c": "r2c_stage", "c2r": "c2r_stage"}
+KIND_NAMES = {"c2c": "c2c_stage", "copy": "redistribute_copy", "r2c": "r2c_stage", "c2r": "c2r_stage",
+              "r2r": "r2r_stage"}
 
 
 def parse():
@@ -378,7 +381,9 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": "%s %s %s on a %s virtual-rank grid, forward+backward, %s path"
-                               % ("x".join(map(str, shape)), kind, "complex64" if prec == "f32" else "complex128",
+                               % ("x".join(map(str, shape)), kind,
+                                  ("float32" if prec == "f32" else "float64") if kind == "r2r"
+                                  else ("complex64" if prec == "f32" else "complex128"),
                                   "x".join(map(str, grid)), args.path),
                    "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path,
                    "placement": list(plan.placement), "tuning": plan.tuning()},

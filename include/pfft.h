@@ -32,7 +32,11 @@
  * complex128 for PFFT_F64.  A PFFT_R2C plan takes a real array (float or
  * double) and produces the half spectrum N_{d-1}/2+1 along the last axis
  * (footnote of Sec. 2); its backward is the matching complex-to-real
- * transform, which ignores the imaginary parts of bins 0 and N/2.
+ * transform, which ignores the imaginary parts of bins 0 and N/2.  A PFFT_R2R
+ * plan (pfft_plan_create_r2r) applies per axis a real-to-real cosine or sine
+ * transform of type II forward and its inverse of type III backward, on real
+ * data in every layout (the "similar" transforms the method carries, Sec. 1);
+ * its per-axis factor is 1/(2 N_m), with which type III undoes type II.
  *
  * Memory.  The library never allocates device memory.  The caller allocates
  * the device state (pfft_device_state_bytes), binds it once
@@ -60,7 +64,13 @@ extern "C" {
 
 typedef struct pfft_plan_s *pfft_plan;
 
-enum { PFFT_C2C = 0, PFFT_R2C = 1 };
+enum { PFFT_C2C = 0, PFFT_R2C = 1, PFFT_R2R = 2 };
+/* Real-to-real transform of one axis (forward type; the backward applies its
+   inverse):  PFFT_DCT2: Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2N), inverse
+   Y_k = x_0 + 2 sum_{j>0} x_j cos(pi j (2k+1) / 2N);  PFFT_DST2:
+   Y_k = 2 sum_j x_j sin(pi (2j+1) (k+1) / 2N), inverse
+   Y_k = (-1)^k x_{N-1} + 2 sum_{j<N-1} x_j sin(pi (j+1) (2k+1) / 2N). */
+enum { PFFT_DCT2 = 0, PFFT_DST2 = 1 };
 enum { PFFT_F32 = 0, PFFT_F64 = 1 };
 enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 
@@ -113,7 +123,8 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *   grid_ndim, grid_dims: the virtual process grid, 1 <= grid_ndim < ndim,
  *     every extent >= 1; P = product of grid_dims virtual ranks.  A direction
  *     may be larger than the axis it splits (those ranks get empty blocks).
- *   precision: PFFT_F32 or PFFT_F64.  kind: PFFT_C2C or PFFT_R2C.
+ *   precision: PFFT_F32 or PFFT_F64.  kind: PFFT_C2C or PFFT_R2C (PFFT_R2R
+ *     plans come from pfft_plan_create_r2r).
  *   norm: PFFT_NORM_*.
  *   chain: NULL for the paper's rule, else 2*nsteps ints {dir, new_axis}: step
  *     s moves grid direction dir onto axis new_axis (which must be whole
@@ -129,6 +140,19 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim,
                      const int *grid_dims, int precision, int kind, int norm, const int *chain,
                      int nsteps, unsigned flags);
+
+/*
+ * Create a real-to-real plan (kind PFFT_R2R): as pfft_plan_create, with
+ * kinds[m] (PFFT_DCT2 or PFFT_DST2) the forward transform of axis m.  Every
+ * layout holds real values (float for PFFT_F32, double for PFFT_F64).  Axis
+ * lengths need a radix plan (2^a <= 4096 or 3*2^a <= 3072), else
+ * PFFT_EUNSUPPORTED.  The adjoints are the transposed transforms (type III
+ * with its first input element doubled for the cosine, its last for the
+ * sine; type II with that output element halved).
+ */
+int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim,
+                         const int *grid_dims, int precision, const int *kinds, int norm,
+                         const int *chain, int nsteps, unsigned flags);
 
 /*
  * Performance knobs of a plan (results never change).  tile_*: 0 default
@@ -266,7 +290,7 @@ int pfft_validate_plan(pfft_plan plan);
  * host synchronisation).  pfft_profile_read waits for the logged launches,
  * fills up to max_entries records (oldest first), sets *n to the number
  * logged, and clears the log.  kind: 0 complex transform, 1 redistribution
- * copy, 2 real-to-complex, 3 complex-to-real; direction: 0 forward, 1 backward,
+ * copy, 2 real-to-complex, 3 complex-to-real, 4 real-to-real; direction: 0 forward, 1 backward,
  * 2 adjoint of forward, 3 adjoint of backward, 4 pfft_redistribute; bytes: the
  * launch's algorithmic traffic (source read once + destination written once).
  * Not for use while a call on the plan is being captured into a graph.

@@ -59,6 +59,8 @@ def load():
     sigs = {
         "pfft_plan_create": [ctypes.POINTER(vp), c_int, i64p, c_int, ip, c_int, c_int, c_int, ip, c_int,
                              ctypes.c_uint],
+        "pfft_plan_create_r2r": [ctypes.POINTER(vp), c_int, i64p, c_int, ip, c_int, ip, c_int, ip, c_int,
+                                 ctypes.c_uint],
         "pfft_plan_destroy": [vp],
         "pfft_plan_set_tuning": [vp, ctypes.POINTER(Tuning)],
         "pfft_plan_get_tuning": [vp, ctypes.POINTER(Tuning)],

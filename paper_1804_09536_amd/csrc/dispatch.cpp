@@ -23,6 +23,7 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
         return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
     }
     case KIND_COPY: return copy_config(N, cfg);
+    case KIND_R2R: return r2r_config(prec, N, contig, variant, cfg);
     case KIND_R2C:
     case KIND_C2R: {
         if (!contig) return -1;
@@ -36,13 +37,15 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
 int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelConfig &cfg, size_t esize,
                  const StageArgs &a, hipStream_t s)
 {
-    if (cfg.id < 0 && kind != KIND_COPY) return (int)dft_launch(prec, N, kind, contig, sign, cfg, a, s);
+    if (cfg.id < 0 && kind != KIND_COPY && kind != KIND_R2R)
+        return (int)dft_launch(prec, N, kind, contig, sign, cfg, a, s);
     switch (kind) {
     case KIND_C2C:
         return (int)(prec == 0 ? c2c_launch_f32(N, contig, sign, cfg, a, s) : c2c_launch_f64(N, contig, sign, cfg, a, s));
     case KIND_COPY: return (int)copy_launch(esize, cfg, a, s);
     case KIND_R2C:
     case KIND_C2R: return (int)real_launch(prec, N, kind, cfg, a, s);
+    case KIND_R2R: return (int)r2r_launch(prec, N, contig, cfg, a, s);
     default: return (int)hipErrorInvalidValue;
     }
 }

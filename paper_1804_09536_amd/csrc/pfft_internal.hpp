@@ -57,12 +57,17 @@ enum StageKind : int32_t {
     KIND_COPY = 1,  // pure permutation of lines (redistribution)
     KIND_R2C = 2,   // real line of N -> N/2+1 bins
     KIND_C2R = 3,   // N/2+1 bins -> real line of N
+    KIND_R2R = 4,   // real line -> real line (cosine / sine transform of type II, or its inverse of type III)
 };
 
 // Flags of a stage launch.
 enum StageFlags : int32_t {
     SF_HALVE_INTERIOR = 1,   // C2R: halve bins 0<k<N-k first (adjoint of R2C)
     SF_DOUBLE_INTERIOR = 2,  // R2C: double bins 0<k<N-k after (adjoint of C2R)
+    SF_R2R_INVERSE = 4,      // R2R: type III (the inverse) instead of type II
+    SF_R2R_SINE = 8,         // R2R: sine instead of cosine transform
+    SF_R2R_ADJOINT = 16,     // R2R: the transpose of the transform (type III: special input
+                             // element doubled; type II: special output element halved)
 };
 
 struct StageArgs {
@@ -70,7 +75,8 @@ struct StageArgs {
     void *dst;
     Side side[2];
     const Tile *tiles;
-    const void *twiddle;  // N entries e^{-2 pi i m / N} (R2C/C2R: N/2-point table + N-point post table)
+    const void *twiddle;  // N entries e^{-2 pi i m / N} (R2C/C2R: N/2-point table + N-point post table;
+                          // R2R: N-point table + e^{-i pi k / 2N}, k < N, in twiddle2)
     const void *twiddle2;
     int64_t ntiles;
     double scale;

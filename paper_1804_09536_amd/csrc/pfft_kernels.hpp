@@ -45,5 +45,7 @@ int dft_config(int prec, int N, int kind, KernelConfig *cfg);
 hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
                       hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+int r2r_config(int prec, int N, int contig, int variant, KernelConfig *cfg);
+hipError_t r2r_launch(int prec, int N, int contig, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 
 }  // namespace pfft

@@ -160,6 +160,7 @@ struct Launch {
     int src = 0, dst = 0;  // layout ids
     int sign = -1;
     int scale_axis = -1;   // axis whose 1/N_m factor may apply (-1: none)
+    int sine = 0;          // R2R: sine (1) or cosine (0) transform
     // device blob offsets
     size_t off_tiles = 0;
     int64_t ntiles = 0;
@@ -184,6 +185,7 @@ struct pfft_plan_s {
     std::vector<std::array<int, kMaxDims>> dirs;  // per chain layout
     std::vector<Layout> layouts;                  // 0..nlayouts-1: spectral; then extras
     int real0 = -1;                               // id of the real input layout (R2C)
+    int r2r[kMaxDims] = {};                       // R2R: per axis PFFT_DCT2 or PFFT_DST2
     std::vector<std::pair<int, int>> sched;       // (chain layout, axis), forward order
     std::vector<Launch> fwd, bwd;
     std::vector<Launch> up, down;  // redistribution between chain neighbours
@@ -195,7 +197,7 @@ struct pfft_plan_s {
     bool has_chain = false;
     void *dev = nullptr;
     size_t spec_bytes = 0;
-    size_t elem = 8;  // complex element bytes
+    size_t elem = 8;  // element bytes of the spectral layouts (complex; real for R2R)
     // optional per-launch timing
     bool profiling = false;
     struct Prof {
@@ -473,7 +475,7 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
         return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
     const pfft_tuning &tu = p->tuning;
-    const int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R)
+    const int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
                             ? (ln.contig ? tu.tile_contig : tu.tile_strided)
                             : 0;
     int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
@@ -488,6 +490,9 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     } else if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) {
         ln.off_tw = twiddle_table(p, ln.N / 2 > 0 ? ln.N / 2 : 1);
         ln.off_tw2 = twiddle_table(p, ln.N);
+    } else if (ln.kind == KIND_R2R) {
+        ln.off_tw = twiddle_table(p, ln.N);
+        ln.off_tw2 = twiddle_table(p, 4 * ln.N);  // its first N entries are e^{-i pi k / 2N}
     }
     // runs shorter than a tile are chained only for the Stockham stage kernels
     build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig);
@@ -579,6 +584,7 @@ static int build_direction(pfft_plan_s *p, const std::vector<std::array<int, 5>>
         ln.dst = tdst;
         ln.sign = sign;
         ln.scale_axis = axis;
+        ln.sine = (kind == KIND_R2R && p->r2r[axis] == PFFT_DST2) ? 1 : 0;
         if (kind == KIND_R2C) ln.N = (int)p->layouts[tsrc].shape[axis];
         else if (kind == KIND_C2R) ln.N = (int)p->layouts[tdst].shape[axis];
         else ln.N = (int)p->layouts[tdst].shape[axis];
@@ -643,7 +649,7 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     if (p->kind == PFFT_R2C) spec[nd - 1] = p->shape[nd - 1] / 2 + 1;
     for (int li = 0; li < p->nlayouts; li++) add_layout(p, spec, ng, p->grid, p->dirs[li].data());
     if (p->kind == PFFT_R2C) p->real0 = add_layout(p, p->shape, ng, p->grid, p->dirs[0].data());
-    p->elem = p->precision == PFFT_F32 ? 8 : 16;
+    p->elem = (p->precision == PFFT_F32 ? 8 : 16) / (p->kind == PFFT_R2R ? 2 : 1);
     p->spec_bytes = (size_t)p->layouts[0].total() * p->elem;
 
     const int last = p->nlayouts - 1;
@@ -665,7 +671,7 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     for (int k = 0; k < K; k++) {
         int li = p->sched[k].first, axis = p->sched[k].second;
         int dst = place(fwd_place, k, li, k + 1 < K ? p->sched[k + 1].first : last, last);
-        int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : KIND_C2C;
+        int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : p->kind == PFFT_R2R ? KIND_R2R : KIND_C2C;
         fsteps.push_back({where, li, dst, axis, kind});
         where = dst;
     }
@@ -673,7 +679,7 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     for (int k = 0; k < K; k++) {
         int li = p->sched[K - 1 - k].first, axis = p->sched[K - 1 - k].second;
         int dst = place(bwd_place, k, li, k + 1 < K ? p->sched[K - 2 - k].first : 0, 0);
-        int kind = KIND_C2C;
+        int kind = p->kind == PFFT_R2R ? KIND_R2R : KIND_C2C;
         if (k == K - 1 && p->kind == PFFT_R2C) {
             kind = KIND_C2R;
             dst = p->real0;
@@ -719,7 +725,8 @@ static pfft_tuning default_tuning()
 static double axis_scale(const pfft_plan_s *p, int axis, bool forward_factors)
 {
     if (axis < 0) return 1.0;
-    double n = (double)p->shape[axis];
+    // real-to-real: the type III transform undoes type II up to 2N
+    double n = (double)p->shape[axis] * (p->kind == PFFT_R2R ? 2.0 : 1.0);
     if (p->norm == PFFT_NORM_FORWARD) return forward_factors ? 1.0 / n : 1.0;
     if (p->norm == PFFT_NORM_BACKWARD) return forward_factors ? 1.0 : 1.0 / n;
     return 1.0;
@@ -781,6 +788,18 @@ static size_t launch_esize(const pfft_plan_s *p, const Launch &ln)
     return p->elem;
 }
 
+// Kernel flags of a launch in a chain of direction `sign`.  chain_flags:
+// SF_HALVE_INTERIOR / SF_DOUBLE_INTERIOR on the adjoint chains; real-to-real
+// stages turn them into SF_R2R_ADJOINT, complex stages ignore them.
+static int stage_flags(const Launch &ln, int sign, int chain_flags)
+{
+    if (ln.kind == KIND_R2R)
+        return (sign > 0 ? SF_R2R_INVERSE : 0) | (ln.sine ? SF_R2R_SINE : 0) |
+               ((chain_flags & (SF_HALVE_INTERIOR | SF_DOUBLE_INTERIOR)) ? SF_R2R_ADJOINT : 0);
+    if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) return chain_flags;
+    return 0;
+}
+
 static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
                       int flags, hipStream_t stream, int direction = 4)
 {
@@ -792,6 +811,7 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
         if (!ea || !eb) return fail(PFFT_EHIP, "hipEventCreate failed");
         if (hipEventRecord(ea, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
     }
+    flags = stage_flags(ln, sign, flags);
     const StageArgs a = stage_args(p, ln, (const uint8_t *)p->dev, src, dst, scale, flags);
     int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
     if (rc != 0) return fail(PFFT_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
@@ -802,10 +822,6 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
     return PFFT_OK;
 }
 
-// Run a launch list with ping-pong buffers so the last launch writes `out`.
-// mode 0: forward factors from norm on forward, 1: backward factors.
-// Source and destination buffer of every launch of a list that reads `in`
-// and must end in `out`, ping-ponging through the workspace.
 // Buffers of a launch list: launch k reads srcs[k] and writes dsts[k]; the
 // last one writes `out`.  Intermediates ping-pong between `out` and one
 // workspace buffer (two when `out` is real), or, with PFFT_DESTROY_INPUT and a
@@ -868,6 +884,9 @@ static int work_buffers(const pfft_plan_s *p)
     return used;
 }
 
+// Run a launch list so that the last launch writes `out` (buffers as
+// assign_buffers chooses); forward_factors selects the norm's forward or
+// backward per-axis factors.
 static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out, void *work,
                     bool forward_factors, int sign, int r2c_flags, hipStream_t stream, int direction)
 {
@@ -881,9 +900,7 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
     for (int k = 0; k < n; k++) {
         const Launch &ln = list[k];
         double scale = (ln.kind == KIND_COPY) ? 1.0 : axis_scale(p, ln.scale_axis, forward_factors);
-        int flags = 0;
-        if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) flags = r2c_flags;
-        int rc = run_launch(p, ln, srcs[k], dsts[k], scale, sign, flags, stream, direction);
+        int rc = run_launch(p, ln, srcs[k], dsts[k], scale, sign, r2c_flags, stream, direction);
         if (rc) return rc;
     }
     return PFFT_OK;
@@ -1144,10 +1161,9 @@ static void batch_fill_args(pfft_batch_s *b)
 
 extern "C" {
 
-int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim, const int *grid_dims,
-                     int precision, int kind, int norm, const int *chain, int nsteps, unsigned flags)
+static int create_plan(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim, const int *grid_dims,
+                       int precision, int kind, const int *r2r, int norm, const int *chain, int nsteps, unsigned flags)
 {
-    PFFT_GUARD_BEGIN
     if (!out) return fail(PFFT_EINVAL, "null plan pointer");
     *out = nullptr;
     if (!global_shape || !grid_dims) return fail(PFFT_EINVAL, "null shape or grid");
@@ -1162,7 +1178,12 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     }
     if (P > (int64_t)1 << 20) return fail(PFFT_EGRID, "too many virtual ranks");
     if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
-    if (kind != PFFT_C2C && kind != PFFT_R2C) return fail(PFFT_EDTYPE, "bad kind");
+    if (kind != PFFT_C2C && kind != PFFT_R2C && kind != PFFT_R2R) return fail(PFFT_EDTYPE, "bad kind");
+    if (kind == PFFT_R2R) {
+        if (!r2r) return fail(PFFT_EINVAL, "real-to-real plans need a transform kind per axis");
+        for (int m = 0; m < ndim; m++)
+            if (r2r[m] != PFFT_DCT2 && r2r[m] != PFFT_DST2) return fail(PFFT_EDTYPE, "bad real-to-real kind");
+    }
     if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
     if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK | PFFT_DESTROY_INPUT)) !=
             0 ||
@@ -1181,6 +1202,8 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     p->kind = kind;
     p->norm = norm;
     p->flags = flags;
+    if (kind == PFFT_R2R)
+        for (int m = 0; m < ndim; m++) p->r2r[m] = r2r[m];
     p->tuning = default_tuning();
     if (chain) {
         p->has_chain = true;
@@ -1193,6 +1216,24 @@ int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int 
     }
     *out = p;
     return PFFT_OK;
+}
+
+int pfft_plan_create(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim, const int *grid_dims,
+                     int precision, int kind, int norm, const int *chain, int nsteps, unsigned flags)
+{
+    PFFT_GUARD_BEGIN
+    if (kind == PFFT_R2R) return fail(PFFT_EDTYPE, "real-to-real plans are created with pfft_plan_create_r2r");
+    return create_plan(out, ndim, global_shape, grid_ndim, grid_dims, precision, kind, nullptr, norm, chain, nsteps,
+                       flags);
+    PFFT_GUARD_END
+}
+
+int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, int grid_ndim, const int *grid_dims,
+                         int precision, const int *kinds, int norm, const int *chain, int nsteps, unsigned flags)
+{
+    PFFT_GUARD_BEGIN
+    return create_plan(out, ndim, global_shape, grid_ndim, grid_dims, precision, PFFT_R2R, kinds, norm, chain, nsteps,
+                       flags);
     PFFT_GUARD_END
 }
 
@@ -1534,7 +1575,7 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
             else
                 assign_buffers(p, list, out, in, work, srcs, dsts);
             double scale = ln.kind == KIND_COPY ? 1.0 : axis_scale(p, ln.scale_axis, direction == 0);
-            StageArgs a = stage_args(p, ln, dev + b->blob_off[m], srcs[g.k], dsts[g.k], scale, 0);
+            StageArgs a = stage_args(p, ln, dev + b->blob_off[m], srcs[g.k], dsts[g.k], scale, stage_flags(ln, sign, 0));
             int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
             if (rc != 0) return fail(PFFT_EHIP, std::string("batch launch: ") + hipGetErrorString((hipError_t)rc));
         }

@@ -18,7 +18,10 @@ _DT = {
     ("c2c", "f64"): (torch.complex128, torch.complex128),
     ("r2c", "f32"): (torch.float32, torch.complex64),
     ("r2c", "f64"): (torch.float64, torch.complex128),
+    ("r2r", "f32"): (torch.float32, torch.float32),
+    ("r2r", "f64"): (torch.float64, torch.float64),
 }
+R2R_KINDS = {"dct2": 0, "dst2": 1}
 
 
 def _stream_handle(device) -> ctypes.c_void_p:
@@ -33,9 +36,12 @@ class Plan:
     """A distributed multidimensional FFT over a virtual process grid.
 
     shape: global array shape (the real shape for kind="r2c").
+    kind: "c2c", "r2c" or "r2r" (real-to-real: the argument r2r names the
+          forward transform of each axis, "dct2" or "dst2"; the backward
+          applies the inverse of type III).
     grid: virtual process grid dims (1 <= len(grid) < len(shape)).
     precision: "f32" (complex64) or "f64" (complex128).
-    kind: "c2c" or "r2c".  norm: "forward" (the paper's), "backward", "none".
+    norm: "forward" (the paper's), "backward", "none".
     chain: None for the paper's rule, else [(grid_dir, new_axis), ...].
     path: "fused" (redistribution fused into the transform's load),
           "unfused" (standalone redistribution kernel) or "pack_realign"
@@ -59,7 +65,7 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
                  norm: str = "forward", chain=None, path: str = "fused", device=None,
-                 layouts_only: bool = False, placement=None, destroy_input: bool = False):
+                 layouts_only: bool = False, placement=None, destroy_input: bool = False, r2r=None):
         lib = _lib.load()
         self.shape = tuple(int(x) for x in shape)
         self.grid = tuple(int(x) for x in grid)
@@ -73,6 +79,12 @@ class Plan:
         self.chain = None if chain is None else [tuple(int(v) for v in s) for s in chain]
         self.device = torch.device(device if device is not None else "cuda")
         self.in_dtype, self.spec_dtype = _DT[(kind, precision)]
+        if kind == "r2r":
+            self.r2r = tuple(r2r) if r2r is not None else ("dct2",) * len(self.shape)
+            if len(self.r2r) != len(self.shape) or any(k not in R2R_KINDS for k in self.r2r):
+                raise ValueError("r2r: one of %s per axis" % sorted(R2R_KINDS))
+        else:
+            self.r2r = None
         h = ctypes.c_void_p()
         shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
         grd = (ctypes.c_int * len(self.grid))(*self.grid)
@@ -81,12 +93,19 @@ class Plan:
         else:
             flat = [v for s in self.chain for v in s]
             ch, nsteps = (ctypes.c_int * max(1, len(flat)))(*flat), len(self.chain)
-        st = lib.pfft_plan_create(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd,
-                                  0 if precision == "f32" else 1, 0 if kind == "c2c" else 1, NORMS[norm],
-                                  ch, nsteps, PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0)
-                                  | (_lib.PLACEMENTS[self.placement[0]] << 3) | (_lib.PLACEMENTS[self.placement[1]] << 5)
-                                  | (_lib.PFFT_DESTROY_INPUT if self.destroy_input else 0))
-        check(st, "pfft_plan_create")
+        flags = (PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0)
+                 | (_lib.PLACEMENTS[self.placement[0]] << 3) | (_lib.PLACEMENTS[self.placement[1]] << 5)
+                 | (_lib.PFFT_DESTROY_INPUT if self.destroy_input else 0))
+        prec = 0 if precision == "f32" else 1
+        if kind == "r2r":
+            kinds = (ctypes.c_int * len(self.shape))(*[R2R_KINDS[k] for k in self.r2r])
+            st = lib.pfft_plan_create_r2r(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd, prec, kinds,
+                                          NORMS[norm], ch, nsteps, flags)
+            check(st, "pfft_plan_create_r2r")
+        else:
+            st = lib.pfft_plan_create(ctypes.byref(h), len(self.shape), shp, len(self.grid), grd, prec,
+                                      {"c2c": 0, "r2c": 1}[kind], NORMS[norm], ch, nsteps, flags)
+            check(st, "pfft_plan_create")
         self._h = h
         n = ctypes.c_int()
         check(lib.pfft_num_layouts(h, ctypes.byref(n)), "pfft_num_layouts")
@@ -156,7 +175,7 @@ class Plan:
         buf = (_lib.ProfileEntry * max_entries)()
         n = ctypes.c_int()
         check(_lib.load().pfft_profile_read(self._h, max_entries, buf, ctypes.byref(n)), "pfft_profile_read")
-        kinds = {0: "c2c", 1: "copy", 2: "r2c", 3: "c2r"}
+        kinds = {0: "c2c", 1: "copy", 2: "r2c", 3: "c2r", 4: "r2r"}
         return [dict(kind=kinds.get(e.kind, "?"), axis=e.axis, contig=bool(e.contig), length=e.length,
                      direction=e.direction, ms=e.ms, bytes=e.bytes) for e in buf[:min(n.value, max_entries)]]
 

@@ -114,3 +114,33 @@ def test_destroy_input_workspace(shape, grid, kind, placement, path, plain, dest
     assert a.workspace_bytes() == plain * one
     assert b.workspace_bytes() == destroyed * one
     b.validate()
+
+
+def test_r2r_plan_creation_checks():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    shp = (ctypes.c_int64 * 3)(16, 12, 8)
+    grd = (ctypes.c_int * 2)(2, 2)
+    ok = (ctypes.c_int * 3)(0, 1, 0)
+    bad = (ctypes.c_int * 3)(0, 7, 0)
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, ok, 0, None, 0, 0) == 0
+    lib.pfft_plan_destroy(h)
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, bad, 0, None, 0, 0) == -4
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, None, 0, None, 0, 0) == -1
+    assert lib.pfft_plan_create(ctypes.byref(h), 3, shp, 2, grd, 0, 2, 0, None, 0, 0) == -4
+    odd = (ctypes.c_int64 * 3)(16, 5, 8)   # length 5 has no radix plan for the cosine stage
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, odd, 2, grd, 0, ok, 0, None, 0, 0) == -5
+
+
+def test_r2r_layouts_match_oracle_and_validate():
+    from paper_1804_09536_amd.plan import Plan
+    shape, grid = (24, 12, 48), (3, 2)
+    p = Plan(shape, grid, kind="r2r", r2r=("dst2", "dct2", "dst2"))
+    ch = oracle.Chain.paper(shape, grid, kind="r2r", r2r=("dst2", "dct2", "dst2"))
+    for li in range(p.num_layouts):
+        lay = ch.layout(li)
+        offs = lay.offsets()
+        for r in range(lay.nranks):
+            assert p.local_block(li, r) == (lay.block(r)[0], lay.block(r)[1], offs[r])
+    assert p.buffer_numel(0) == 24 * 12 * 48
+    p.validate()
