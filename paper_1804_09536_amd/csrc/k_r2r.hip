@@ -24,14 +24,19 @@
 
 namespace pfft {
 
-// Launch shape: the tile width of the complex stage's variant V (H = 1), at
-// most 512 threads.
+// Launch shape: the tile width of the complex stage's variant V (one LDS
+// portion), at most 512 threads.  (Two LDS portions measured slower here and
+// round differently: the compiler contracts multiply-adds differently in that
+// instantiation.)
 template <typename T, int N, bool CONTIG, int V>
 struct R2RCfg {
+    using D = C2CDefault<T, N, CONTIG>;
     using B = C2CVariant<T, N, CONTIG, V>;
     static constexpr int P = fft_points(N);
     static constexpr int TPL = N / P;
-    static constexpr int W = (B::exists && B::H == 1) ? B::W : C2CDefault<T, N, CONTIG>::W;
+    static constexpr int H = 1;
+    static constexpr int W = (B::exists && B::H == 1) ? B::W : D::W;
+    static constexpr int WL = W;
     static constexpr int nl_for(int nl) { return (TPL * W / nl > 512 && nl < W) ? nl_for(nl * 2) : nl; }
     static constexpr int NL = nl_for(1);
     static constexpr int SLOTS = W / NL;
@@ -43,12 +48,17 @@ __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restri
 {
     using T2 = typename V2<T>::type;
     constexpr int P = S::P, TPL = S::TPL, NL = S::NL, W = S::W, SLOTS = S::SLOTS;
-    using LT = LdsTile<T2, N, W, CONTIG>;
+    constexpr int H = S::H, WL = S::WL;
+    using LT = LdsTile<T2, N, WL, CONTIG>;
     constexpr int RLINE = N + 1, RROW = W + 1;  // real staging (aliases the exchange LDS)
     static_assert((CONTIG ? W * RLINE : N * RROW) <= 2 * LT::SIZE, "real staging must fit");
+    constexpr bool TQL = N * sizeof(T2) <= 8192;  // quarter-wave twiddles staged in LDS when small
     __shared__ T2 lds[LT::SIZE];
     __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
-    const T2 *tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);
+    __shared__ T2 tql[TQL ? N : 1];
+    if constexpr (TQL)
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tql[i] = ((const T2 *)a.twiddle2)[i];
+    const T2 *tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);  // tql is first read after the barrier below
     T *rl = (T *)lds;
     auto ridx = [](int w, int j) { return CONTIG ? w * RLINE + j : j * RROW + w; };
 
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restri
     __syncthreads();
 
     // 2. the complex FFT input, point k = jt + m*TPL of each line
-    const T2 *__restrict__ tq = (const T2 *)a.twiddle2;  // e^{-i pi k / 2N}
+    const T2 *tq = TQL ? (const T2 *)tql : (const T2 *)a.twiddle2;  // e^{-i pi k / 2N}
     T2 v[NL][P];
 #pragma unroll
     for (int l = 0; l < NL; l++)
@@ -110,18 +120,19 @@ __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restri
                 if (adj && jk == special) xk *= (T)2;
                 if (adj && k > 0 && jn == special) xn *= (T)2;
                 const T2 w = tq[k];
-                // e^{+i pi k/2N} (xk - i xn) / 2
-                v[l][m].x = (T)0.5 * (w.x * xk - w.y * xn);
-                v[l][m].y = (T)0.5 * (-w.x * xn - w.y * xk);
+                // e^{+i pi k/2N} (xk - i xn) / 2, with the fused multiply-adds
+                // spelled out (the same rounding in every launch shape)
+                v[l][m].x = (T)0.5 * fma(w.x, xk, -(w.y * xn));
+                v[l][m].y = (T)-0.5 * fma(w.x, xn, w.y * xk);
             }
         }
     __syncthreads();
 
     // 3. the N-point transform (forward for type II, inverse for type III)
     if (inverse)
-        fft_passes<T2, N, W, CONTIG, 1, NL, 1, 0>(v, wl, jt, lds, tw);
+        fft_passes<T2, N, WL, CONTIG, 1, NL, H, 0>(v, wl, jt, lds, tw);
     else
-        fft_passes<T2, N, W, CONTIG, -1, NL, 1, 0>(v, wl, jt, lds, tw);
+        fft_passes<T2, N, WL, CONTIG, -1, NL, H, 0>(v, wl, jt, lds, tw);
     __syncthreads();
 
     // 4. outputs reordered through LDS, then stored in natural order
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restri
             const int k = jt + m * TPL;
             if (!inverse) {
                 const T2 w = tq[k];
-                T y = (T)2 * (w.x * v[l][m].x - w.y * v[l][m].y) * scale;
+                T y = (T)2 * fma(w.x, v[l][m].x, -(w.y * v[l][m].y)) * scale;
                 const int q = sine ? N - 1 - k : k;
                 if (adj && q == special) y *= (T)0.5;
                 rl[ridx(wl[l], q)] = y;
@@ -173,7 +184,8 @@ static hipError_t r2r_launch_v(const StageArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// variants: 0 the default tile, 1 half as many lines (as the complex stages')
+// variants: 0 the default tile, 1 half as many lines (as the complex
+// stages'); others use the default
 template <typename T>
 static int r2r_config_t(int N, int contig, int variant, KernelConfig *cfg)
 {

@@ -85,7 +85,7 @@ def test_r2r_knobs_placements_and_destroy_input_are_neutral():
     for placement in [(x, x) for x in names] + [("direct", "gather")]:
         for destroy in (False, True):
             p = Plan(shape, grid, kind="r2r", r2r=kinds, placement=placement, destroy_input=destroy)
-            for tc, ts in itertools.product((0, 1), (0, 1)):
+            for tc, ts in itertools.product((0, 1), (0, 1, 3)):
                 p.set_tuning(tile_contig=tc, tile_strided=ts)
                 assert _host(p.forward(_to_dev(u))).tobytes() == ref.tobytes(), (placement, destroy, tc, ts)
                 assert _host(p.backward(_to_dev(ref))).tobytes() == ref_b.tobytes(), (placement, destroy, tc, ts)
