@@ -100,8 +100,25 @@ def cpu_baseline(shape, grid, kind, chain, u_np):
     oracle.backward(ch, y)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(dt * 1e3, 1), "unit": "ms per forward+backward", "cores": cores, "kind": "oracle",
-            "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)"}
+    out = {"value": round(dt * 1e3, 1), "unit": "ms per forward+backward", "cores": cores, "kind": "oracle",
+           "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)"}
+    # the same oracle on one thread, on a bounded sample: the 256^3 pencil on
+    # 4x4 ranks, in a child process so that its OpenMP runtime starts with one thread
+    import subprocess
+    code = ("import time, numpy as np, oracle\n"
+            "ch = oracle.Chain.paper((256, 256, 256), (4, 4))\n"
+            "x = np.random.default_rng(1).uniform(-1, 1, 2 * 256 ** 3).view(np.complex128)\n"
+            "t = time.perf_counter(); oracle.backward(ch, oracle.forward(ch, x)); print(time.perf_counter() - t)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT,
+                           timeout=300)
+        t1 = float(r.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": round(t1 * 1e3, 1), "unit": "ms per forward+backward", "cores": 1,
+                                "sample": "256x256x256 complex128 on a 4x4 virtual-rank grid, one thread"}
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        out["single_thread"] = None
+    return out
 
 
 BATCH_SHAPES = [
@@ -204,7 +221,7 @@ def bench_grad(args):
     def grad_step():
         u.grad = None
         uh = pad.forward(u, plan)
-        loss = torch.sum(w * (uh.real * uh.real + uh.imag * uh.imag))
+        loss = pad.weighted_energy(uh, w)
         loss.backward()
 
     y = plan.empty(plan.num_layouts - 1)

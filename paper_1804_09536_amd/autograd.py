@@ -74,6 +74,27 @@ def global_indices(plan: Plan, layout: int, real: bool = False, device=None):
     return [torch.cat(p).to(device) for p in parts]
 
 
+class _WeightedEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, uh, w):
+        wu = w * uh
+        ctx.save_for_backward(wu)
+        return torch.vdot(uh, wu).real
+
+    @staticmethod
+    def backward(ctx, g):
+        (wu,) = ctx.saved_tensors
+        return wu * (2 * g), None
+
+
+def weighted_energy(uh: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+    """sum_k w(k) |uh(k)|^2 for a real weight w on the same buffer, with its
+    gradient 2 w uh (torch's convention for complex inputs) formed in one
+    pass: the loss of the differentiation workload without the chain of
+    elementwise kernels autograd would record for it."""
+    return _WeightedEnergy.apply(uh, w)
+
+
 def wavenumber_weight(plan: Plan, layout: int = -1) -> torch.Tensor:
     """w(k) = |k|^2 on a (spectral) layout: signed integer wavenumbers on the
     full axes, 0..N/2 on the half axis of a real-input plan."""

@@ -36,18 +36,21 @@ def test_weight_matches_oracle():
     assert np.array_equal(w, expect)
 
 
-def _loss(p, u, w):
+def _loss(p, u, w, fused=False):
     uh = pad.forward(u, p)
+    if fused:
+        return pad.weighted_energy(uh, w)
     return torch.sum(w * (uh.real ** 2 + uh.imag ** 2))
 
 
-def test_exact_central_differences_16cubed():
+@pytest.mark.parametrize("fused", [False, True])
+def test_exact_central_differences_16cubed(fused):
     # the loss is quadratic, so central differences are exact for any step
     p = Plan((16, 16, 16), (4, 4), precision="f64", kind="r2c")
     w = pad.wavenumber_weight(p)
     u0 = inputs.gaussian_real(p.buffer_numel(0, real=True), [24], np.float64)
     u = torch.from_numpy(u0).cuda().requires_grad_()
-    loss = _loss(p, u, w)
+    loss = _loss(p, u, w, fused)
     loss.backward()
     g = u.grad.cpu().numpy()
     rng = np.random.default_rng(7)
@@ -55,21 +58,22 @@ def test_exact_central_differences_16cubed():
         e = torch.zeros_like(u)
         e[i] = 1.0
         with torch.no_grad():
-            lp = float(_loss(p, u + e, w))
-            lm = float(_loss(p, u - e, w))
+            lp = float(_loss(p, u + e, w, fused))
+            lm = float(_loss(p, u - e, w, fused))
         fd = (lp - lm) / 2.0
         assert abs(fd - g[i]) <= 1e-9 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
-def test_gradient_256cubed_matches_oracle():
+@pytest.mark.parametrize("fused", [False, True])
+def test_gradient_256cubed_matches_oracle(fused):
     shape, grid = (256, 256, 256), (4, 4)
-    print("case", shape, grid, flush=True)
+    print("case", shape, grid, fused, flush=True)
     p = Plan(shape, grid, kind="r2c")
     ch = oracle.Chain.paper(shape, grid, kind="r2c")
     w = pad.wavenumber_weight(p)
     u0 = inputs.gaussian_real(p.buffer_numel(0, real=True), [5], np.float32)
     u = torch.from_numpy(u0).cuda().requires_grad_()
-    loss = _loss(p, u, w.to(torch.float32))
+    loss = _loss(p, u, w.to(torch.float32), fused)
     loss.backward()
     g = u.grad.cpu().numpy()
     wg = w.cpu().numpy()
