@@ -23,7 +23,8 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
         return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
     }
     case KIND_COPY: return copy_config(N, cfg);
-    case KIND_R2R: return r2r_config(prec, N, contig, variant, cfg);
+    case KIND_R2R:
+        return prec == 0 ? r2r_config_f32(N, contig, variant, cfg) : r2r_config_f64(N, contig, variant, cfg);
     case KIND_R2C:
     case KIND_C2R: {
         if (!contig) return -1;
@@ -45,7 +46,8 @@ int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelCo
     case KIND_COPY: return (int)copy_launch(esize, cfg, a, s);
     case KIND_R2C:
     case KIND_C2R: return (int)real_launch(prec, N, kind, cfg, a, s);
-    case KIND_R2R: return (int)r2r_launch(prec, N, contig, cfg, a, s);
+    case KIND_R2R:
+        return (int)(prec == 0 ? r2r_launch_f32(N, contig, cfg, a, s) : r2r_launch_f64(N, contig, cfg, a, s));
     default: return (int)hipErrorInvalidValue;
     }
 }

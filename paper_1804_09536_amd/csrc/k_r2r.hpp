@@ -1,0 +1,484 @@
+// k_r2r.hpp -- real-to-real partial transforms: the cosine and sine
+// transforms of type II and their inverses of type III, along any axis of a
+// layout, with the same gather/scatter addressing as the complex stages (so a
+// redistribution is fused into the load or the store as for the FFT).  The
+// method carries such "similar" transforms unchanged (Sec. 1 and the
+// conclusions); the definitions, unnormalised:
+//   type II cosine:  Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2N)
+//   type III cosine: Y_k = x_0 + 2 sum_{j>=1} x_j cos(pi j (2k+1) / 2N)
+//   type II sine:    Y_k = 2 sum_j x_j sin(pi (2j+1) (k+1) / 2N)
+//   type III sine:   Y_k = (-1)^k x_{N-1} + 2 sum_{j<N-1} x_j sin(pi (j+1) (2k+1) / 2N)
+//
+// Each line goes through one complex FFT (Makhoul's reordering):
+//   type II:  v_n = x_{p(n)} with p(n) = 2n for n < ceil(N/2), 2(N-1-n)+1
+//             after; V = FFT_N(v); Y_k = 2 Re(e^{-i pi k/2N} V_k).
+//   type III: V_k = e^{+i pi k/2N} (X_k - i X_{N-k}) / 2 (X_N = 0);
+//             v = unnormalised inverse FFT_N of V; y_{p(n)} = 2 Re v_n.
+//   sine:     type II of x_j (-1)^j, output reversed; type III of the
+//             reversed input, output times (-1)^k.
+// For even N >= 4 the real sequence v is packed as z_n = v_{2n} + i v_{2n+1}
+// and transformed at half length M = N/2, with the usual pairing of bins k
+// and M-k (as in the real-to-complex stage):
+//   V_k = (Z_k + conj Z_{M-k})/2 - (i/2) e^{-2 pi i k/N} (Z_k - conj Z_{M-k}),
+//   Y_k = 2 Re(w_k V_k), Y_{N-k} = -2 Im(w_k V_k), w_k = e^{-i pi k/2N};
+// and backwards Z'_k = (V_k + conj V_{M-k}) + i e^{2 pi i k/N} (V_k - conj V_{M-k}),
+// whose unnormalised inverse FFT_M is v_{2n} + i v_{2n+1}.
+// The lines of a tile are staged as real values in LDS twice (reordering in,
+// reordering out), so global accesses stay in natural order.
+#pragma once
+
+#include "fft_device.hpp"
+#include "k_c2c_impl.hpp"
+#include "pfft_kernels.hpp"
+
+namespace pfft {
+
+// Launch shape: the tile width of the complex stage's variant V (one LDS
+// portion), at most 512 threads.  (Two LDS portions measured slower here and
+// round differently: the compiler contracts multiply-adds differently in that
+// instantiation.)
+template <typename T, int N, bool CONTIG, int V>
+struct R2RCfg {
+    using D = C2CDefault<T, N, CONTIG>;
+    using B = C2CVariant<T, N, CONTIG, V>;
+    static constexpr int P = fft_points(N);
+    static constexpr int TPL = N / P;
+    static constexpr int H = 1;
+    static constexpr int W = (B::exists && B::H == 1) ? B::W : D::W;
+    static constexpr int WL = W;
+    static constexpr int nl_for(int nl) { return (TPL * W / nl > 512 && nl < W) ? nl_for(nl * 2) : nl; }
+    static constexpr int NL = nl_for(1);
+    static constexpr int SLOTS = W / NL;
+    static constexpr int NT = TPL * SLOTS;
+};
+
+template <typename T, int N, bool CONTIG, class S>
+__global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restrict__ tiles)
+{
+    using T2 = typename V2<T>::type;
+    constexpr int P = S::P, TPL = S::TPL, NL = S::NL, W = S::W, SLOTS = S::SLOTS;
+    constexpr int H = S::H, WL = S::WL;
+    using LT = LdsTile<T2, N, WL, CONTIG>;
+    constexpr int RLINE = N + 1, RROW = W + 1;  // real staging (aliases the exchange LDS)
+    constexpr int STAGE = CONTIG ? W * RLINE : N * RROW;
+    constexpr int LDS_N = LT::SIZE > (STAGE + 1) / 2 ? LT::SIZE : (STAGE + 1) / 2;
+    constexpr bool TQL = N * sizeof(T2) <= 8192;  // quarter-wave twiddles staged in LDS when small
+    __shared__ T2 lds[LDS_N];
+    __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
+    __shared__ T2 tql[TQL ? N : 1];
+    if constexpr (TQL)
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tql[i] = ((const T2 *)a.twiddle2)[i];
+    const T2 *tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);  // tql is first read after the barrier below
+    T *rl = (T *)lds;
+    auto ridx = [](int w, int j) { return CONTIG ? w * RLINE + j : j * RROW + w; };
+
+    const int tid = threadIdx.x;
+    const int jt = CONTIG ? tid % TPL : tid / SLOTS;
+    const int slot = CONTIG ? tid / TPL : tid % SLOTS;
+    int wl[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) wl[l] = slot + l * SLOTS;
+    const Tile &t = tiles[blockIdx.x];
+    const int count = t.count;
+    const bool inverse = (a.flags & SF_R2R_INVERSE) != 0;
+    const bool sine = (a.flags & SF_R2R_SINE) != 0;
+    const bool adj = (a.flags & SF_R2R_ADJOINT) != 0;
+    const int special = sine ? N - 1 : 0;  // the element types II and III weigh differently
+    constexpr int h = (N + 1) / 2;
+
+    // 1. the tile's lines, natural order, into LDS (all loads first)
+    SideAddr<P> src;
+    src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
+    const T *__restrict__ in = (const T *)a.src;
+    T xr[NL][P];
+    if (count == W) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) xr[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
+    } else {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) xr[l][m] = wl[l] < count ? in[src.off[m] + wl[l] * src.stride[m]] : (T)0;
+    }
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < P; m++) rl[ridx(wl[l], jt + m * TPL)] = xr[l][m];
+    __syncthreads();
+
+    // 2. the complex FFT input, point k = jt + m*TPL of each line
+    const T2 *tq = TQL ? (const T2 *)tql : (const T2 *)a.twiddle2;  // e^{-i pi k / 2N}
+    T2 v[NL][P];
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const int k = jt + m * TPL;
+            if (!inverse) {
+                const int p = k < h ? 2 * k : 2 * (N - 1 - k) + 1;
+                T x = rl[ridx(wl[l], p)];
+                if (sine && (p & 1)) x = -x;
+                v[l][m].x = x;
+                v[l][m].y = (T)0;
+            } else {
+                const int jk = sine ? N - 1 - k : k;
+                const int jn = sine ? k - 1 : N - k;
+                T xk = rl[ridx(wl[l], jk)];
+                T xn = k == 0 ? (T)0 : rl[ridx(wl[l], jn)];
+                if (adj && jk == special) xk *= (T)2;
+                if (adj && k > 0 && jn == special) xn *= (T)2;
+                const T2 w = tq[k];
+                // e^{+i pi k/2N} (xk - i xn) / 2, with the fused multiply-adds
+                // spelled out (the same rounding in every launch shape)
+                v[l][m].x = (T)0.5 * fma(w.x, xk, -(w.y * xn));
+                v[l][m].y = (T)-0.5 * fma(w.x, xn, w.y * xk);
+            }
+        }
+    __syncthreads();
+
+    // 3. the N-point transform (forward for type II, inverse for type III)
+    if (inverse)
+        fft_passes<T2, N, WL, CONTIG, 1, NL, H, 0>(v, wl, jt, lds, tw);
+    else
+        fft_passes<T2, N, WL, CONTIG, -1, NL, H, 0>(v, wl, jt, lds, tw);
+    __syncthreads();
+
+    // 4. outputs reordered through LDS, then stored in natural order
+    const T scale = (T)a.scale;
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const int k = jt + m * TPL;
+            if (!inverse) {
+                const T2 w = tq[k];
+                T y = (T)2 * fma(w.x, v[l][m].x, -(w.y * v[l][m].y)) * scale;
+                const int q = sine ? N - 1 - k : k;
+                if (adj && q == special) y *= (T)0.5;
+                rl[ridx(wl[l], q)] = y;
+            } else {
+                const int q = k < h ? 2 * k : 2 * (N - 1 - k) + 1;
+                T y = (T)2 * v[l][m].x * scale;
+                if (sine && (q & 1)) y = -y;
+                rl[ridx(wl[l], q)] = y;
+            }
+        }
+    __syncthreads();
+    SideAddr<P> dst;
+    dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
+    T *__restrict__ out = (T *)a.dst;
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < P; m++)
+            if (wl[l] < count) out[dst.off[m] + wl[l] * dst.stride[m]] = rl[ridx(wl[l], jt + m * TPL)];
+}
+
+// Half-length stage of N = 2M points: S is the launch shape of the M-point
+// transform; each thread also loads and stores 2P of the line's N reals.
+template <typename T, int M, bool CONTIG, class S>
+__global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__restrict__ tiles)
+{
+    using T2 = typename V2<T>::type;
+    constexpr int N = 2 * M;
+    constexpr int P = S::P, TPL = S::TPL, NL = S::NL, W = S::W, SLOTS = S::SLOTS;
+    using LT = LdsTile<T2, M, W, CONTIG>;
+    constexpr int RLINE = N + 1, RROW = W + 1;  // real staging (aliases the exchange LDS)
+    constexpr int STAGE = CONTIG ? W * RLINE : N * RROW;
+    constexpr int LDS_N = LT::SIZE > (STAGE + 1) / 2 ? LT::SIZE : (STAGE + 1) / 2;
+    constexpr bool PT = 2 * (M + 1) * sizeof(T2) <= 8192;  // post table staged in LDS when small
+    __shared__ T2 lds[LDS_N];
+    __shared__ T2 twl[TwiddleStage<T2, M>::SIZE];
+    __shared__ T2 ptl[PT ? 2 * (M + 1) : 1];
+    if constexpr (PT)
+        for (int i = threadIdx.x; i < 2 * (M + 1); i += blockDim.x) ptl[i] = ((const T2 *)a.twiddle2)[i];
+    const T2 *tw = TwiddleStage<T2, M>::stage(twl, a.twiddle);  // ptl is first read after the barrier below
+    const T2 *te = PT ? (const T2 *)ptl : (const T2 *)a.twiddle2;  // e^{-2 pi i k/N}, k <= M
+    const T2 *tq = te + (M + 1);                                     // e^{-i pi k/2N}, k <= M
+    T *rl = (T *)lds;
+    auto ridx = [](int w, int j) { return CONTIG ? w * RLINE + j : j * RROW + w; };
+
+    const int tid = threadIdx.x;
+    const int jt = CONTIG ? tid % TPL : tid / SLOTS;
+    const int slot = CONTIG ? tid / TPL : tid % SLOTS;
+    int wl[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) wl[l] = slot + l * SLOTS;
+    const Tile &t = tiles[blockIdx.x];
+    const int count = t.count;
+    const bool inverse = (a.flags & SF_R2R_INVERSE) != 0;
+    const bool sine = (a.flags & SF_R2R_SINE) != 0;
+    const bool adj = (a.flags & SF_R2R_ADJOINT) != 0;
+    const int special = sine ? N - 1 : 0;
+    constexpr int h = M;  // ceil(N/2)
+
+    // 1. the tile's lines, natural order, into LDS (all loads first); the
+    // adjoint of type II doubles the special input element of type III
+    SideAddr<2 * P> src;
+    src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
+    const T *__restrict__ in = (const T *)a.src;
+    T xr[NL][2 * P];
+    if (count == W) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < 2 * P; m++) xr[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
+    } else {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < 2 * P; m++)
+                xr[l][m] = wl[l] < count ? in[src.off[m] + wl[l] * src.stride[m]] : (T)0;
+    }
+    const bool dbl = adj && inverse;
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < 2 * P; m++) {
+            const int j = jt + m * TPL;
+            rl[ridx(wl[l], j)] = (dbl && j == special) ? (T)2 * xr[l][m] : xr[l][m];
+        }
+    __syncthreads();
+
+    // 2. the M-point input, point k = jt + m*TPL of each line
+    T2 v[NL][P];
+    if (!inverse) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int n = jt + m * TPL;
+                const int p0 = 2 * n < h ? 4 * n : 2 * (N - 1 - 2 * n) + 1;
+                const int p1 = 2 * n + 1 < h ? 4 * n + 2 : 2 * (N - 2 - 2 * n) + 1;
+                T x0 = rl[ridx(wl[l], p0)], x1 = rl[ridx(wl[l], p1)];
+                if (sine && (p0 & 1)) x0 = -x0;
+                if (sine && (p1 & 1)) x1 = -x1;
+                v[l][m].x = x0;
+                v[l][m].y = x1;
+            }
+    } else {
+        // X in the type III input order (the sine transform reads it reversed)
+        auto X = [&](int w, int j) { return rl[ridx(w, sine ? N - 1 - j : j)]; };
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const int kc = M - k;  // 1..M
+                // V_k = e^{+i pi k/2N} (X_k - i X_{N-k}) / 2 and the same at M-k
+                const T xk = X(wl[l], k), xnk = k == 0 ? (T)0 : X(wl[l], N - k);
+                const T xc = X(wl[l], kc), xnc = X(wl[l], N - kc);
+                const T2 qk = tq[k], qc = tq[kc];
+                T2 vk, vc;
+                vk.x = (T)0.5 * fma(qk.x, xk, -(qk.y * xnk));
+                vk.y = (T)-0.5 * fma(qk.x, xnk, qk.y * xk);
+                vc.x = (T)0.5 * fma(qc.x, xc, -(qc.y * xnc));
+                vc.y = (T)-0.5 * fma(qc.x, xnc, qc.y * xc);
+                // Z'_k = (V_k + conj V_c) + i e^{+2 pi i k/N} (V_k - conj V_c)
+                const T2 s = {vk.x + vc.x, vk.y - vc.y};
+                const T2 d = {vk.x - vc.x, vk.y + vc.y};
+                const T2 e = te[k];  // e^{-2 pi i k/N}; its conjugate here
+                const T2 ed = {fma(e.x, d.x, e.y * d.y), fma(e.x, d.y, -(e.y * d.x))};
+                v[l][m].x = s.x - ed.y;
+                v[l][m].y = s.y + ed.x;
+            }
+    }
+    __syncthreads();
+
+    // 3. the M-point transform
+    if (inverse)
+        fft_passes<T2, M, W, CONTIG, 1, NL, 1, 0>(v, wl, jt, lds, tw);
+    else
+        fft_passes<T2, M, W, CONTIG, -1, NL, 1, 0>(v, wl, jt, lds, tw);
+    __syncthreads();
+
+    // 4. outputs into registers (type II pairs bins k and M-k through LDS)
+    const T scale = (T)a.scale;
+    T yr[NL][2 * P];
+    int yq[2 * P];  // output position of yr[.][m] (the same for every line)
+    if (!inverse) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) lds[LT::idx(wl[l], jt + m * TPL)] = v[l][m];
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const T2 zk = v[l][m];
+                T2 zc = lds[LT::idx(wl[l], k == 0 ? 0 : M - k)];
+                zc.y = -zc.y;
+                // X_k = (Z_k + conj Z_c)/2 - (i/2) e^{-2 pi i k/N} (Z_k - conj Z_c)
+                const T2 sm = {(T)0.5 * (zk.x + zc.x), (T)0.5 * (zk.y + zc.y)};
+                const T2 df = {(T)0.5 * (zk.x - zc.x), (T)0.5 * (zk.y - zc.y)};
+                const T2 e = te[k];
+                const T2 ed = {fma(e.x, df.x, -(e.y * df.y)), fma(e.x, df.y, e.y * df.x)};
+                const T2 xk = {sm.x + ed.y, sm.y - ed.x};
+                const T2 q = tq[k];
+                const T2 wx = {fma(q.x, xk.x, -(q.y * xk.y)), fma(q.x, xk.y, q.y * xk.x)};
+                // Y_k = 2 Re(w_k X_k); Y_{N-k} = -2 Im(w_k X_k) (k > 0); bin M from Z_0 (k = 0)
+                T y0 = (T)2 * wx.x * scale;
+                T y1;
+                int q1;
+                if (k == 0) {
+                    const T xm = zk.x - zk.y;  // X_M (real)
+                    y1 = (T)2 * tq[M].x * xm * scale;
+                    q1 = M;
+                } else {
+                    y1 = (T)-2 * wx.y * scale;
+                    q1 = N - k;
+                }
+                int q0 = k;
+                if (sine) {
+                    q0 = N - 1 - q0;
+                    q1 = N - 1 - q1;
+                }
+                if (adj && q0 == special) y0 *= (T)0.5;
+                if (adj && q1 == special) y1 *= (T)0.5;
+                yr[l][2 * m] = y0;
+                yr[l][2 * m + 1] = y1;
+                if (l == 0) {
+                    yq[2 * m] = q0;
+                    yq[2 * m + 1] = q1;
+                }
+            }
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const int n = jt + m * TPL;
+            yq[2 * m] = 2 * n < h ? 4 * n : 2 * (N - 1 - 2 * n) + 1;
+            yq[2 * m + 1] = 2 * n + 1 < h ? 4 * n + 2 : 2 * (N - 2 - 2 * n) + 1;
+        }
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                T y0 = (T)2 * v[l][m].x * scale, y1 = (T)2 * v[l][m].y * scale;
+                if (sine && (yq[2 * m] & 1)) y0 = -y0;
+                if (sine && (yq[2 * m + 1] & 1)) y1 = -y1;
+                yr[l][2 * m] = y0;
+                yr[l][2 * m + 1] = y1;
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < 2 * P; m++) rl[ridx(wl[l], yq[m])] = yr[l][m];
+    __syncthreads();
+
+    // 5. natural-order stores
+    SideAddr<2 * P> dst;
+    dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
+    T *__restrict__ out = (T *)a.dst;
+#pragma unroll
+    for (int l = 0; l < NL; l++)
+#pragma unroll
+        for (int m = 0; m < 2 * P; m++)
+            if (wl[l] < count) out[dst.off[m] + wl[l] * dst.stride[m]] = rl[ridx(wl[l], jt + m * TPL)];
+}
+
+template <typename T, int N, bool CONTIG, int V>
+static void r2r_shape(KernelConfig *cfg)
+{
+    using S = R2RCfg<T, N, CONTIG, V>;
+    cfg->W = S::W;
+    cfg->threads = S::NT;
+    cfg->id = V;
+    cfg->resident = 0;
+}
+
+template <typename T, int N, bool CONTIG, int V>
+static hipError_t r2r_launch_full(const StageArgs &a, hipStream_t s)
+{
+    using S = R2RCfg<T, N, CONTIG, V>;
+    hipLaunchKernelGGL((k_r2r<T, N, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
+template <typename T, int M, bool CONTIG, int V>
+static hipError_t r2r_launch_half(const StageArgs &a, hipStream_t s)
+{
+    using S = R2RCfg<T, M, CONTIG, V>;
+    hipLaunchKernelGGL((k_r2r_half<T, M, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
+inline bool half_length_supported(int M)
+{
+    switch (M) {
+#define PFFT_CASE(n) \
+    case n:          \
+        return true;
+        PFFT_FOR_EACH_N(PFFT_CASE)
+#undef PFFT_CASE
+    default:
+        return false;
+    }
+}
+
+inline bool r2r_half_length_impl(int N) { return N >= 4 && N % 2 == 0 && half_length_supported(N / 2); }
+
+// variants: 0 the default tile, 1 half as many lines (as the complex
+// stages'); others use the default.  Even lengths use the half-length kernel
+// (tile shapes of the N/2-point transform), lengths 2 and 3 the full one.
+template <typename T>
+static int r2r_config_t(int N, int contig, int variant, KernelConfig *cfg)
+{
+    const int v = variant == 1 ? 1 : 0;
+    if (r2r_half_length_impl(N)) {
+        switch (N / 2) {
+#define PFFT_CASE(n)                                                                          \
+    case n:                                                                                   \
+        if (contig)                                                                           \
+            (v == 1 ? r2r_shape<T, n, true, 1> : r2r_shape<T, n, true, 0>)(cfg);             \
+        else                                                                                  \
+            (v == 1 ? r2r_shape<T, n, false, 1> : r2r_shape<T, n, false, 0>)(cfg);           \
+        return 0;
+            PFFT_FOR_EACH_N(PFFT_CASE)
+#undef PFFT_CASE
+        }
+        return -1;
+    }
+    if (N == 2) {
+        (contig ? (v == 1 ? r2r_shape<T, 2, true, 1> : r2r_shape<T, 2, true, 0>)
+                : (v == 1 ? r2r_shape<T, 2, false, 1> : r2r_shape<T, 2, false, 0>))(cfg);
+        return 0;
+    }
+    if (N == 3) {
+        (contig ? (v == 1 ? r2r_shape<T, 3, true, 1> : r2r_shape<T, 3, true, 0>)
+                : (v == 1 ? r2r_shape<T, 3, false, 1> : r2r_shape<T, 3, false, 0>))(cfg);
+        return 0;
+    }
+    return -1;
+}
+
+template <typename T>
+static hipError_t r2r_launch_t(int N, int contig, int variant, const StageArgs &a, hipStream_t s)
+{
+    if (r2r_half_length_impl(N)) {
+        switch (N / 2) {
+#define PFFT_CASE(n)                                                                                          \
+    case n:                                                                                                   \
+        if (contig)                                                                                           \
+            return variant == 1 ? r2r_launch_half<T, n, true, 1>(a, s) : r2r_launch_half<T, n, true, 0>(a, s); \
+        return variant == 1 ? r2r_launch_half<T, n, false, 1>(a, s) : r2r_launch_half<T, n, false, 0>(a, s);
+            PFFT_FOR_EACH_N(PFFT_CASE)
+#undef PFFT_CASE
+        }
+        return hipErrorInvalidValue;
+    }
+    if (N == 2)
+        return contig ? (variant == 1 ? r2r_launch_full<T, 2, true, 1>(a, s) : r2r_launch_full<T, 2, true, 0>(a, s))
+                      : (variant == 1 ? r2r_launch_full<T, 2, false, 1>(a, s) : r2r_launch_full<T, 2, false, 0>(a, s));
+    if (N == 3)
+        return contig ? (variant == 1 ? r2r_launch_full<T, 3, true, 1>(a, s) : r2r_launch_full<T, 3, true, 0>(a, s))
+                      : (variant == 1 ? r2r_launch_full<T, 3, false, 1>(a, s) : r2r_launch_full<T, 3, false, 0>(a, s));
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pfft

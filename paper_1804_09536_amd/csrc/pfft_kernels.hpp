@@ -45,7 +45,13 @@ int dft_config(int prec, int N, int kind, KernelConfig *cfg);
 hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
                       hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
-int r2r_config(int prec, int N, int contig, int variant, KernelConfig *cfg);
-hipError_t r2r_launch(int prec, int N, int contig, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+int r2r_config_f32(int N, int contig, int variant, KernelConfig *cfg);
+int r2r_config_f64(int N, int contig, int variant, KernelConfig *cfg);
+hipError_t r2r_launch_f32(int N, int contig, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+hipError_t r2r_launch_f64(int N, int contig, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+// Real-to-real stages of even length N >= 4 run one N/2-point transform
+// (twiddles: the N/2-point table and the post table), the others one
+// N-point transform (the N-point and 4N-point tables).
+bool r2r_half_length(int N);
 
 }  // namespace pfft

@@ -281,6 +281,33 @@ static size_t twiddle_table(pfft_plan_s *p, int n)
     return off;
 }
 
+// Post/pre-processing table of the half-length real-to-real stage of length
+// N = 2M: e^{-2 pi i k / N} for k = 0..M, then e^{-i pi k / 2N} for k = 0..M.
+static size_t r2r_post_table(pfft_plan_s *p, int N)
+{
+    auto it = p->tw_cache.find(-N);
+    if (it != p->tw_cache.end()) return it->second.first;
+    const int M = N / 2;
+    std::vector<double> t(4 * (size_t)(M + 1));
+    for (int k = 0; k <= M; k++) {
+        const double a = 2.0 * M_PI * (double)k / (double)N;
+        const double b = 2.0 * M_PI * (double)k / (4.0 * (double)N);
+        t[2 * k] = cos(a);
+        t[2 * k + 1] = -sin(a);
+        t[2 * (M + 1 + k)] = cos(b);
+        t[2 * (M + 1 + k) + 1] = -sin(b);
+    }
+    size_t off;
+    if (p->precision == PFFT_F32) {
+        std::vector<float> f(t.begin(), t.end());
+        off = blob_put(p, f.data(), f.size() * 4);
+    } else {
+        off = blob_put(p, t.data(), t.size() * 8);
+    }
+    p->tw_cache[-N] = {off, 0};
+    return off;
+}
+
 struct LineRec {
     int32_t rank[2];
     int64_t O[2], E[2], I[2];
@@ -490,6 +517,9 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     } else if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) {
         ln.off_tw = twiddle_table(p, ln.N / 2 > 0 ? ln.N / 2 : 1);
         ln.off_tw2 = twiddle_table(p, ln.N);
+    } else if (ln.kind == KIND_R2R && r2r_half_length(ln.N)) {
+        ln.off_tw = twiddle_table(p, ln.N / 2);
+        ln.off_tw2 = r2r_post_table(p, ln.N);
     } else if (ln.kind == KIND_R2R) {
         ln.off_tw = twiddle_table(p, ln.N);
         ln.off_tw2 = twiddle_table(p, 4 * ln.N);  // its first N entries are e^{-i pi k / 2N}

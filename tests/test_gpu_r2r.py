@@ -37,6 +37,7 @@ CASES = [
     ((3, 2, 6), (4, 3), ("dst2", "dct2", "dct2"), "f32", "forward"),        # empty blocks
     ((16, 24, 512), (8, 8), ("dct2", "dst2", "dct2"), "f32", "forward"),    # long contiguous lines
     ((512, 4, 8), (2, 2), ("dst2", "dct2", "dst2"), "f64", "forward"),      # long strided lines
+    ((6, 4, 8192), (2, 2), ("dct2", "dct2", "dst2"), "f32", "forward"),     # half-length 4096-point stage
 ]
 
 
