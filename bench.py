@@ -34,6 +34,8 @@ WORKLOADS = {
     "pencil512_4x4": ((512, 512, 512), (4, 4), "c2c", "f32", None),
     "pencil512_32x16": ((512, 512, 512), (32, 16), "c2c", "f32", None),
     "slab512_thin": ((512, 512, 512), (512,), "c2c", "f32", None),
+    # the largest buffers the kernels address (just under 2^31 elements, 12 GiB each)
+    "max1536": ((1536, 1024, 1024), (8, 8), "c2c", "f32", None),
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
     "r2c512": ((512, 512, 512), (8, 8), "r2c", "f32", None),
@@ -284,11 +286,17 @@ def main():
     plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev,
                 placement=placement).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
-    if kind == "c2c":
-        u_np = inputs.uniform_complex(n_in, [4], np.complex64 if prec == "f32" else np.complex128)
+    # arrays beyond 2^28 elements are drawn on the device (no host copy, no CPU baseline)
+    big = n_in > (1 << 28)
+    if big and kind == "c2c":
+        u_np = None
+        x = inputs.uniform_complex_device(n_in, 4, plan.spec_dtype, dev)
     else:
-        u_np = inputs.gaussian_real(n_in, [2], np.float32 if prec == "f32" else np.float64)
-    x = torch.from_numpy(u_np).to(dev)
+        if kind == "c2c":
+            u_np = inputs.uniform_complex(n_in, [4], np.complex64 if prec == "f32" else np.complex128)
+        else:
+            u_np = inputs.gaussian_real(n_in, [2], np.float32 if prec == "f32" else np.float64)
+        x = torch.from_numpy(u_np).to(dev)
     y = plan.empty(plan.num_layouts - 1)
     z = plan.empty(0, real=(kind == "r2c"))
     work = plan.workspace()
@@ -381,7 +389,7 @@ def main():
         del ref
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and u_np is not None:
         cpu = cpu_baseline(shape, grid, kind, chain, u_np)
 
     out = {

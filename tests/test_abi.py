@@ -144,3 +144,9 @@ def test_r2r_layouts_match_oracle_and_validate():
             assert p.local_block(li, r) == (lay.block(r)[0], lay.block(r)[1], offs[r])
     assert p.buffer_numel(0) == 24 * 12 * 48
     p.validate()
+
+
+def test_buffers_of_2_31_elements_are_refused():
+    # kernels address buffers with 32-bit element offsets: 2^31 elements is one too many
+    assert _create((2048, 1024, 1024), (8, 8)) == -5
+    assert _create((1536, 1024, 1024), (8, 8), flags=4) == 0
