@@ -34,7 +34,9 @@ WORKLOADS = {
     "pencil512_4x4": ((512, 512, 512), (4, 4), "c2c", "f32", None),
     "pencil512_32x16": ((512, 512, 512), (32, 16), "c2c", "f32", None),
     "slab512_thin": ((512, 512, 512), (512,), "c2c", "f32", None),
-    # the largest buffers the kernels address (just under 2^31 elements, 12 GiB each)
+    # long lines: 1024^3, and the largest buffers the kernels address (just
+    # under 2^31 elements, 12 GiB each)
+    "c2c1024": ((1024, 1024, 1024), (8, 8), "c2c", "f32", None),
     "max1536": ((1536, 1024, 1024), (8, 8), "c2c", "f32", None),
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),

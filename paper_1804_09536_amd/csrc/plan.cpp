@@ -502,9 +502,11 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
         return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
     const pfft_tuning &tu = p->tuning;
-    const int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
-                            ? (ln.contig ? tu.tile_contig : tu.tile_strided)
-                            : 0;
+    int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
+                      ? (ln.contig ? tu.tile_contig : tu.tile_strided)
+                      : 0;
+    // 5: the measured choice per length (wider tiles for long strided lines)
+    if (variant == 5) variant = ln.contig ? 1 : (ln.N >= 1024 ? 4 : 3);
     int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
     if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0)
@@ -746,7 +748,7 @@ static pfft_tuning default_tuning()
 {
     pfft_tuning t;
     t.tile_contig = 1;
-    t.tile_strided = 3;
+    t.tile_strided = 5;  // by length: 3 below 1024 points, 4 from 1024 on
     t.resident_contig = 0;
     t.resident_strided = 0;
     return t;
@@ -1271,7 +1273,7 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
 {
     PFFT_GUARD_BEGIN
     if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
-    if (t->tile_contig < 0 || t->tile_contig > 4 || t->tile_strided < 0 || t->tile_strided > 4 ||
+    if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 5 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again

@@ -20,7 +20,7 @@ import torch
 from . import inputs
 from .plan import Plan
 
-TILES = (0, 1, 2, 3, 4)
+TILES = (0, 1, 2, 3, 4, 5)
 RESIDENT = (0, 1)
 PLACEMENTS = ("gather", "scatter", "direct", "final")
 
