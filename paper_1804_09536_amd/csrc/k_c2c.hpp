@@ -138,8 +138,8 @@ struct C2CWorker {
         const T2 *__restrict__ in = (const T2 *)a.src;
         int lo[NL];
         if constexpr (!CONTIG) line_offsets(t, 0, lo);
-        if (fast && CONTIG && a.side[0].R == 0) {
-            // whole source lines along the last axis: streaming loads
+        if (fast && CONTIG) {
+            // lines along the last axis (whole, or gathered in pieces): streaming loads
 #pragma unroll
             for (int l = 0; l < NL; l++)
 #pragma unroll
