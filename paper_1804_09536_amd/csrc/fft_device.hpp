@@ -82,16 +82,25 @@ __device__ __forceinline__ void store_stream(V *p, V v)
     }
 }
 
-// Streaming (non-temporal) load of one complex value.
+// Streaming (non-temporal) load of one complex value or a pair of them.
 template <typename V>
 __device__ __forceinline__ V load_stream(const V *p)
 {
     using E = decltype(p->x);
-    typedef E n2 __attribute__((ext_vector_type(2)));
-    n2 t = __builtin_nontemporal_load((const n2 *)p);
     V v;
-    v.x = t.x;
-    v.y = t.y;
+    if constexpr (sizeof(V) == 2 * sizeof(E)) {
+        typedef E n2 __attribute__((ext_vector_type(2)));
+        n2 t = __builtin_nontemporal_load((const n2 *)p);
+        v.x = t.x;
+        v.y = t.y;
+    } else {
+        typedef E n4 __attribute__((ext_vector_type(4)));
+        n4 t = __builtin_nontemporal_load((const n4 *)p);
+        v.x = t.x;
+        v.y = t.y;
+        v.z = t.z;
+        v.w = t.w;
+    }
     return v;
 }
 
