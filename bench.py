@@ -40,6 +40,7 @@ WORKLOADS = {
     "max1536": ((1536, 1024, 1024), (8, 8), "c2c", "f32", None),
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
+    "pencil512_f64": ((512, 512, 512), (8, 8), "c2c", "f64", None),
     "r2c512": ((512, 512, 512), (8, 8), "r2c", "f32", None),
     # real-to-real: type II cosine transform on every axis (type III back)
     "dct512": ((512, 512, 512), (8, 8), "r2r", "f32", None),
