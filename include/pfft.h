@@ -160,10 +160,10 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * (wider coalesced rows, more LDS), 3 twice as many exchanged through the
  * default LDS in two portions (wider rows at the default LDS size), 4 four
  * times as many with 1024-thread workgroups exchanged in two portions
- * (widest rows, one workgroup per CU), 5 chosen by length (1 for contiguous
- * stages; 3 for strided lines below 1024 points, 4 from 1024 on: the
- * measured best, and the default of tile_strided); lengths without a shape
- * use the default; resident_*: 1 launches only as many
+ * (widest rows, one workgroup per CU), 5 chosen by stage (1 for contiguous
+ * and real-to-real stages; 3 for strided lines below 1024 points, 4 from
+ * 1024 on: the measured best, and the default of tile_strided); lengths
+ * without a shape use the default; resident_*: 1 launches only as many
  * workgroups as the device holds at once, each looping over tiles, 0 one
  * workgroup per tile.  *_contig applies to partial transforms along the last
  * axis (tile_contig also to the real-to-complex and complex-to-real stages,

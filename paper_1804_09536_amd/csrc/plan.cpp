@@ -505,8 +505,9 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
                       ? (ln.contig ? tu.tile_contig : tu.tile_strided)
                       : 0;
-    // 5: the measured choice per length (wider tiles for long strided lines)
-    if (variant == 5) variant = ln.contig ? 1 : (ln.N >= 1024 ? 4 : 3);
+    // 5: the measured choice per length (wider tiles for long strided lines;
+    // real-to-real stages are fastest with more, smaller workgroups)
+    if (variant == 5) variant = (ln.contig || ln.kind == KIND_R2R) ? 1 : (ln.N >= 1024 ? 4 : 3);
     int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
     if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0)
