@@ -18,7 +18,13 @@ MEMBERS = [
     ((32, 32, 32), (4,), "c2c"),         # slab
     ((8, 16, 4, 32), (3, 1, 5), "c2c"),  # 4-D
     ((16, 16, 32), (4, 2), "r2c"),       # real input (per-member launches inside the batch)
+    ((12, 16, 24), (2, 3), "r2r"),       # cosine/sine transforms (per-member launches)
 ]
+R2R = ("dst2", "dct2", "dst2")
+
+
+def _plan(s, g, k, **kw):
+    return Plan(s, g, kind=k, r2r=R2R if k == "r2r" else None, **kw)
 
 
 def _fill(batch):
@@ -35,8 +41,9 @@ def _fill(batch):
 
 
 def test_batch_equals_per_transform_and_oracle():
-    plans = [Plan(s, g, kind=k) for s, g, k in MEMBERS]
+    plans = [_plan(s, g, k) for s, g, k in MEMBERS]
     plans.append(plans[1])  # the same plan twice shares its tables
+    plans.append(_plan((32, 16, 64), (2, 4), "c2c", destroy_input=True))  # no workspace
     b = Batch(plans)
     data = _fill(b)
     b.forward()
@@ -46,7 +53,7 @@ def test_batch_equals_per_transform_and_oracle():
         ref = p.forward(torch.from_numpy(data[m]).cuda())
         torch.cuda.synchronize()
         assert b.outputs[m].cpu().numpy().tobytes() == ref.cpu().numpy().tobytes()
-        ch = oracle.Chain.paper(p.shape, p.grid, kind=p.kind)
+        ch = oracle.Chain.paper(p.shape, p.grid, kind=p.kind, r2r=p.r2r)
         expect = oracle.forward(ch, data[m].astype(np.complex128 if p.kind == "c2c" else np.float64))
         got = b.outputs[m].cpu().numpy()
         assert np.linalg.norm(got - expect) / np.linalg.norm(expect) <= 1e-5
@@ -58,7 +65,7 @@ def test_batch_equals_per_transform_and_oracle():
 
 
 def test_batch_graph_replay():
-    plans = [Plan(s, g, kind=k) for s, g, k in MEMBERS[:3]]
+    plans = [_plan(s, g, k) for s, g, k in MEMBERS[:3]]
     b = Batch(plans)
     data = _fill(b)
     b.forward()
