@@ -295,7 +295,8 @@ int pfft_validate_plan(pfft_plan plan);
  * copy, 2 real-to-complex, 3 complex-to-real, 4 real-to-real; direction: 0 forward, 1 backward,
  * 2 adjoint of forward, 3 adjoint of backward, 4 pfft_redistribute; bytes: the
  * launch's algorithmic traffic (source read once + destination written once).
- * Not for use while a call on the plan is being captured into a graph.
+ * Not for use while a call on the plan is being captured into a graph, nor from
+ * several host threads at once (the log is the plan's own).
  */
 typedef struct {
     int kind;

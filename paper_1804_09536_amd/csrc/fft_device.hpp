@@ -392,15 +392,26 @@ struct SideAddr {
             }
             return;
         }
+        // table lookups in three rounds (every position's block first, then
+        // the blocks' extents and offsets) so each round's loads are in flight
+        // together instead of one dependent chain per position
+        int2 pc[P];
 #pragma unroll
         for (int m = 0; m < P; m++) {
             int j = jt + m * TPL;
             if (j >= N) j = N - 1;  // callers mask positions past the end
-            const int2 pc = sd.pos[j];
-            const long na = sd.na[pc.x];
-            const long base = sd.rank_off[rank + pc.x * sd.R];
-            off[m] = (int)(base + (O * na + pc.y) * E + I);
-            stride[m] = contig ? (int)(na * E) : 1;
+            pc[m] = sd.pos[j];
+        }
+        long na[P], base[P];
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            na[m] = sd.na[pc[m].x];
+            base[m] = sd.rank_off[rank + pc[m].x * sd.R];
+        }
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            off[m] = (int)(base[m] + (O * na[m] + pc[m].y) * E + I);
+            stride[m] = contig ? (int)(na[m] * E) : 1;
         }
     }
 };
