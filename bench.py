@@ -283,8 +283,8 @@ def main():
     shape, grid, kind, prec, chain = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    placement = tuple(args.placement.split(",")) if args.placement else Plan.DEFAULT_PLACEMENT
-    if len(placement) == 1:
+    placement = tuple(args.placement.split(",")) if args.placement else None
+    if placement is not None and len(placement) == 1:
         placement = placement * 2
     plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev,
                 placement=placement).bind()

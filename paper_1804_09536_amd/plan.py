@@ -55,13 +55,13 @@ class Plan:
           alignments are never stored) or "final" (all in the final layout);
           one name for both chains or a (forward, backward) pair.  Same
           results; different access patterns.  The default pair is the
-          fastest measured on the 512^3 pencil workload.
+          fastest measured per kind on the 512^3 pencil workloads.
     destroy_input: the transforms may overwrite a complex input and use it
           for intermediates (no workspace for most c2c plans, one buffer
           instead of two for r2c); a real input is never written.
     """
 
-    DEFAULT_PLACEMENT = ("direct", "gather")
+    DEFAULT_PLACEMENT = {"c2c": ("direct", "gather"), "r2c": ("scatter", "gather"), "r2r": ("direct", "gather")}
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
                  norm: str = "forward", chain=None, path: str = "fused", device=None,
@@ -72,7 +72,7 @@ class Plan:
         self.precision, self.kind, self.norm, self.path = precision, kind, norm, path
         self.destroy_input = bool(destroy_input)
         if placement is None:
-            placement = self.DEFAULT_PLACEMENT
+            placement = self.DEFAULT_PLACEMENT[kind]
         self.placement = (placement, placement) if isinstance(placement, str) else tuple(placement)
         if len(self.placement) != 2 or any(p not in _lib.PLACEMENTS for p in self.placement):
             raise ValueError("placement must be one of %s or a pair of them" % sorted(_lib.PLACEMENTS))
