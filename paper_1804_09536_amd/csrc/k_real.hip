@@ -47,8 +47,21 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
         wl[l] = slot + l * SLOTS;
         valid[l] = wl[l] < count;
     }
+    // the M-point table and the first M entries of the N-point table, staged
+    // in LDS once per workgroup where they are small
+    constexpr bool TW_LDS = TwiddleStage<T2, M>::on;
+    __shared__ T2 twl[TW_LDS ? 2 * M : 1];
     const T2 *__restrict__ tw = (const T2 *)a.twiddle;    // M-point table
     const T2 *__restrict__ tw2 = (const T2 *)a.twiddle2;  // N-point table
+    if constexpr (TW_LDS) {
+        for (int i = tid; i < M; i += S::NT) {
+            twl[i] = tw[i];
+            twl[M + i] = tw2[i];
+        }
+        __syncthreads();
+        tw = twl;
+        tw2 = twl + M;
+    }
     const T scale = (T)a.scale;
     T2 v[NL][P];
 
@@ -57,11 +70,19 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
         SideAddr<P> rs;
         rs.init(a.side[0], t, 0, 2 * jt, 2 * TPL, NR, true);
         const T *__restrict__ in = (const T *)a.src;
+        if (count == W) {
+            // whole real lines, each byte read once: streaming loads
 #pragma unroll
-        for (int l = 0; l < NL; l++)
+            for (int l = 0; l < NL; l++)
 #pragma unroll
-            for (int m = 0; m < P; m++)
-                v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
+                for (int m = 0; m < P; m++) v[l][m] = load_stream((const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]));
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++)
+                    v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
+        }
         fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
         __syncthreads();
 #pragma unroll
@@ -73,6 +94,9 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
         cs.init(a.side[1], t, 1, jt, TPL, M + 1, true);
         T2 *__restrict__ out = (T2 *)a.dst;
         const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
+        // whole destination lines (the half spectrum stays in its block):
+        // streaming stores
+        const bool stream = a.side[1].R == 0;
 #pragma unroll
         for (int l = 0; l < NL; l++) {
             if (!valid[l]) continue;
@@ -90,7 +114,11 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
                 T2 x = c_add(e, c_mul(tw2[k], o));
                 T f = scale;
                 if (dbl && k > 0) f *= (T)2;
-                out[cs.off[m] + wl[l] * cs.stride[m]] = c_scale(x, f);
+                T2 *q = out + cs.off[m] + wl[l] * cs.stride[m];
+                if (stream)
+                    store_stream(q, c_scale(x, f));
+                else
+                    *q = c_scale(x, f);
             }
             if (jt == 0) {
                 // bin M: E_0 - O_0 = Re Z_0 - Im Z_0
@@ -118,7 +146,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
 #pragma unroll
             for (int l = 0; l < NL; l++)
 #pragma unroll
-                for (int m = 0; m < P; m++) v[l][m] = in[cs.off[m] + wl[l] * cs.stride[m]];
+                for (int m = 0; m < P; m++) v[l][m] = load_stream(in + cs.off[m] + wl[l] * cs.stride[m]);
         } else {
 #pragma unroll
             for (int l = 0; l < NL; l++)
@@ -178,11 +206,20 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
         SideAddr<P> rs;
         rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
         T *__restrict__ out = (T *)a.dst;
+        if (count == W && a.side[1].R == 0) {
+            // whole real lines in the destination: streaming stores
 #pragma unroll
-        for (int l = 0; l < NL; l++)
+            for (int l = 0; l < NL; l++)
 #pragma unroll
-            for (int m = 0; m < P; m++)
-                if (valid[l]) *(T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]) = c_scale(v[l][m], scale);
+                for (int m = 0; m < P; m++)
+                    store_stream((T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]), c_scale(v[l][m], scale));
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < P; m++)
+                    if (valid[l]) *(T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]) = c_scale(v[l][m], scale);
+        }
     }
 }
 
