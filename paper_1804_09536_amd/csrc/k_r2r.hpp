@@ -52,6 +52,84 @@ struct R2RCfg {
     static constexpr int NT = TPL * SLOTS;
 };
 
+// Row pieces of a strided real tile (N rows of W adjacent lines): Q reals
+// (16 bytes) per piece, CPR pieces per row; thread `tid` moves piece
+// tid % CPR of rows tid / CPR + i * TPR, i < RPT.  Used for full tiles whose
+// line 0 starts at a multiple of Q elements at every row on both sides (tile
+// flag FLAG: bit 1 for 4-byte reals, bit 0 for 8-byte reals).
+template <typename T, int N, int W, int NT, bool CONTIG>
+struct R2RRows {
+    static constexpr int Q = 16 / (int)sizeof(T);
+    static constexpr int CPR = W / Q > 0 ? W / Q : 1;
+    static constexpr int TPR = NT / CPR > 0 ? NT / CPR : 1;
+    static constexpr int RPT = N / TPR > 0 ? N / TPR : 1;
+    static constexpr bool on = !CONTIG && W % Q == 0 && NT % CPR == 0 && N % TPR == 0 && RPT <= 32;
+    static constexpr int FLAG = sizeof(T) == 4 ? 2 : 1;
+    using V = typename V2<T>::type;  // replaced below for 4-byte reals
+    __device__ static __forceinline__ T get(const V &v, int e) { return e == 0 ? v.x : v.y; }
+    __device__ static __forceinline__ void set(V &v, int e, T x) { (e == 0 ? v.x : v.y) = x; }
+    __device__ static __forceinline__ V load_nt(const V *p) { return load_stream(p); }
+    __device__ static __forceinline__ void store_nt(V *p, V v) { store_stream(p, v); }
+};
+template <int N, int W, int NT, bool CONTIG>
+struct R2RRows<float, N, W, NT, CONTIG> {
+    static constexpr int Q = 4;
+    static constexpr int CPR = W / Q > 0 ? W / Q : 1;
+    static constexpr int TPR = NT / CPR > 0 ? NT / CPR : 1;
+    static constexpr int RPT = N / TPR > 0 ? N / TPR : 1;
+    static constexpr bool on = !CONTIG && W % Q == 0 && NT % CPR == 0 && N % TPR == 0 && RPT <= 32;
+    static constexpr int FLAG = 2;
+    using V = float4;
+    __device__ static __forceinline__ float get(const V &v, int e)
+    {
+        return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+    }
+    __device__ static __forceinline__ void set(V &v, int e, float x)
+    {
+        if (e == 0) v.x = x;
+        else if (e == 1) v.y = x;
+        else if (e == 2) v.z = x;
+        else v.w = x;
+    }
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __device__ static __forceinline__ V load_nt(const V *p)
+    {
+        const f4 t = __builtin_nontemporal_load((const f4 *)p);
+        V v;
+        v.x = t.x;
+        v.y = t.y;
+        v.z = t.z;
+        v.w = t.w;
+        return v;
+    }
+    __device__ static __forceinline__ void store_nt(V *p, V v)
+    {
+        const f4 t = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(t, (f4 *)p);
+    }
+};
+
+// Line pieces of a contiguous real tile (W lines of N adjacent reals): Q
+// reals (16 bytes) per piece, CPL pieces per line; thread `tid` moves piece
+// tid % CPL of lines tid / CPL + i * LG, i < LPT.  Used for full tiles whose
+// aligned groups of Q positions are adjacent and start at a multiple of Q
+// elements in every line on both sides (tile flag FLAG).
+#ifndef PFFT_R2R_WIDE_CONTIG
+#define PFFT_R2R_WIDE_CONTIG 1
+#endif
+template <typename T, int N, int W, int NT, bool CONTIG>
+struct R2RLines {
+    using RW = R2RRows<T, N, W, NT, false>;  // piece type and accessors
+    using V = typename RW::V;
+    static constexpr int Q = RW::Q;
+    static constexpr int CPL = N / Q > 0 ? N / Q : 1;
+    static constexpr int LG = NT / CPL > 0 ? NT / CPL : 1;
+    static constexpr int LPT = W / LG > 0 ? W / LG : 1;
+    static constexpr bool on = PFFT_R2R_WIDE_CONTIG && CONTIG && N % Q == 0 && CPL <= NT && NT % CPL == 0 &&
+                               W % LG == 0 && LPT <= 32;
+    static constexpr int FLAG = RW::FLAG;
+};
+
 template <typename T, int N, bool CONTIG, class S>
 __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restrict__ tiles)
 {
@@ -188,13 +266,25 @@ __global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__r
     constexpr int RLINE = N + 1, RROW = W + 1;  // real staging (aliases the exchange LDS)
     constexpr int STAGE = CONTIG ? W * RLINE : N * RROW;
     constexpr int LDS_N = LT::SIZE > (STAGE + 1) / 2 ? LT::SIZE : (STAGE + 1) / 2;
-    constexpr bool PT = 2 * (M + 1) * sizeof(T2) <= 8192;  // post table staged in LDS when small
+    // The M-point twiddles and the post table are staged in LDS when small;
+    // on contiguous tiles only when that costs no workgroup per CU (160 KB of
+    // LDS per CU), since those stages gain more from tiles in flight (strided
+    // stages measured the other way round).
+    constexpr int LDS_CU = 160 * 1024;
+    constexpr int B_BASE = LDS_N * (int)sizeof(T2);
+    constexpr int B_TW = M * (int)sizeof(T2), B_PT = 2 * (M + 1) * (int)sizeof(T2);
+    constexpr bool TWL = TwiddleStage<T2, M>::on && (!CONTIG || LDS_CU / (B_BASE + B_TW) == LDS_CU / B_BASE);
+    constexpr int B_T = B_BASE + (TWL ? B_TW : 0);
+    constexpr bool PT = B_PT <= 8192 && (!CONTIG || LDS_CU / (B_T + B_PT) == LDS_CU / B_T);
     __shared__ T2 lds[LDS_N];
-    __shared__ T2 twl[TwiddleStage<T2, M>::SIZE];
+    __shared__ T2 twl[TWL ? M : 1];
     __shared__ T2 ptl[PT ? 2 * (M + 1) : 1];
+    // (both are first read after the barrier that ends step 1)
+    if constexpr (TWL)
+        for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = ((const T2 *)a.twiddle)[i];
     if constexpr (PT)
         for (int i = threadIdx.x; i < 2 * (M + 1); i += blockDim.x) ptl[i] = ((const T2 *)a.twiddle2)[i];
-    const T2 *tw = TwiddleStage<T2, M>::stage(twl, a.twiddle);  // ptl is first read after the barrier below
+    const T2 *tw = TWL ? (const T2 *)twl : (const T2 *)a.twiddle;
     const T2 *te = PT ? (const T2 *)ptl : (const T2 *)a.twiddle2;  // e^{-2 pi i k/N}, k <= M
     const T2 *tq = te + (M + 1);                                     // e^{-i pi k/2N}, k <= M
     T *rl = (T *)lds;
@@ -216,30 +306,72 @@ __global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__r
 
     // 1. the tile's lines, natural order, into LDS (all loads first); the
     // adjoint of type II doubles the special input element of type III
-    SideAddr<2 * P> src;
-    src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
     const T *__restrict__ in = (const T *)a.src;
-    T xr[NL][2 * P];
-    if (count == W) {
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < 2 * P; m++) xr[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
-    } else {
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < 2 * P; m++)
-                xr[l][m] = wl[l] < count ? in[src.off[m] + wl[l] * src.stride[m]] : (T)0;
-    }
     const bool dbl = adj && inverse;
+    using RW = R2RRows<T, N, W, S::NT, CONTIG>;
+    using RC = R2RLines<T, N, W, S::NT, CONTIG>;
+    const bool wide = RW::on && count == W && (t.flags & RW::FLAG);
+    const bool wide_c = RC::on && count == W && (t.flags & RC::FLAG);
+    if (wide_c) {
+        // contiguous tile, full and aligned: 16-byte pieces of each line
+        const int q = tid % RC::CPL, r0 = tid / RC::CPL;
+        SideAddr<1> ws;
+        ws.init(a.side[0], t, 0, q * RC::Q, 1, N, true);
+        typename RC::V xv[RC::LPT];
 #pragma unroll
-    for (int l = 0; l < NL; l++)
+        for (int i = 0; i < RC::LPT; i++)  // each byte read once: streaming loads
+            xv[i] = RW::load_nt((const typename RC::V *)(in + ws.off[0] + (r0 + i * RC::LG) * ws.stride[0]));
 #pragma unroll
-        for (int m = 0; m < 2 * P; m++) {
-            const int j = jt + m * TPL;
-            rl[ridx(wl[l], j)] = (dbl && j == special) ? (T)2 * xr[l][m] : xr[l][m];
+        for (int i = 0; i < RC::LPT; i++)
+#pragma unroll
+            for (int e = 0; e < RC::Q; e++) {
+                const int j = q * RC::Q + e;
+                const T x = RW::get(xv[i], e);
+                rl[ridx(r0 + i * RC::LG, j)] = (dbl && j == special) ? (T)2 * x : x;
+            }
+    } else if (wide) {
+        // strided tile, full and aligned: rows of W reals in 16-byte pieces
+        // (any thread may move any piece: the staging decouples the loads
+        // from the transform's point ownership)
+        const int q = tid % RW::CPR, r0 = tid / RW::CPR;
+        SideAddr<RW::RPT> ws;
+        ws.init(a.side[0], t, 0, r0, RW::TPR, N, false);
+        typename RW::V xv[RW::RPT];
+#pragma unroll
+        for (int i = 0; i < RW::RPT; i++) xv[i] = *(const typename RW::V *)(in + ws.off[i] + q * RW::Q);
+#pragma unroll
+        for (int i = 0; i < RW::RPT; i++) {
+            const int j = r0 + i * RW::TPR;
+#pragma unroll
+            for (int e = 0; e < RW::Q; e++) {
+                const T x = RW::get(xv[i], e);
+                rl[ridx(q * RW::Q + e, j)] = (dbl && j == special) ? (T)2 * x : x;
+            }
         }
+    } else {
+        SideAddr<2 * P> src;
+        src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
+        T xr[NL][2 * P];
+        if (count == W) {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < 2 * P; m++) xr[l][m] = in[src.off[m] + wl[l] * src.stride[m]];
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; l++)
+#pragma unroll
+                for (int m = 0; m < 2 * P; m++)
+                    xr[l][m] = wl[l] < count ? in[src.off[m] + wl[l] * src.stride[m]] : (T)0;
+        }
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < 2 * P; m++) {
+                const int j = jt + m * TPL;
+                rl[ridx(wl[l], j)] = (dbl && j == special) ? (T)2 * xr[l][m] : xr[l][m];
+            }
+    }
     __syncthreads();
 
     // 2. the M-point input, point k = jt + m*TPL of each line
@@ -372,9 +504,39 @@ __global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__r
     __syncthreads();
 
     // 5. natural-order stores
+    T *__restrict__ out = (T *)a.dst;
+    if (wide_c) {
+        const int q = tid % RC::CPL, r0 = tid / RC::CPL;
+        SideAddr<1> wd;
+        wd.init(a.side[1], t, 1, q * RC::Q, 1, N, true);
+#pragma unroll
+        for (int i = 0; i < RC::LPT; i++) {
+            typename RC::V y;
+#pragma unroll
+            for (int e = 0; e < RC::Q; e++) RW::set(y, e, rl[ridx(r0 + i * RC::LG, q * RC::Q + e)]);
+            typename RC::V *o = (typename RC::V *)(out + wd.off[0] + (r0 + i * RC::LG) * wd.stride[0]);
+            if (a.side[1].R == 0)
+                RW::store_nt(o, y);  // whole destination lines: streaming stores
+            else
+                *o = y;
+        }
+        return;
+    }
+    if (wide) {
+        const int q = tid % RW::CPR, r0 = tid / RW::CPR;
+        SideAddr<RW::RPT> wd;
+        wd.init(a.side[1], t, 1, r0, RW::TPR, N, false);
+#pragma unroll
+        for (int i = 0; i < RW::RPT; i++) {
+            typename RW::V y;
+#pragma unroll
+            for (int e = 0; e < RW::Q; e++) RW::set(y, e, rl[ridx(q * RW::Q + e, r0 + i * RW::TPR)]);
+            *(typename RW::V *)(out + wd.off[i] + q * RW::Q) = y;
+        }
+        return;
+    }
     SideAddr<2 * P> dst;
     dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
-    T *__restrict__ out = (T *)a.dst;
 #pragma unroll
     for (int l = 0; l < NL; l++)
 #pragma unroll

@@ -464,24 +464,54 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
         off = noff;
         // flag bit 0: in strided mode, every line pair (2i, 2i+1) sits at two
         // adjacent elements starting at an even one, at every position on
-        // both sides (so fp32 line pairs move as 16-byte units)
-        bool even = !contig;
-        if (t.run > 0) even = even && (t.run % 2 == 0) && (t.b0 % 2 == 0) && (t.ostr[0] % 2 == 0) && (t.ostr[1] % 2 == 0);
-        for (int s = 0; s < 2 && even; s++) {
+        // both sides (so fp32 line pairs move as 16-byte units); bit 1: the
+        // same for groups of four lines (four 4-byte reals per 16 bytes)
+        // In contiguous mode (real-to-real stages only, the one kernel that
+        // reads them there) the bits say the same of the positions of a line:
+        // each aligned pair (quad) of positions is adjacent in one block and
+        // starts at an even (multiple-of-four) element for every line.
+        bool even = !contig, quad = !contig;
+        if (contig && ln.kind == KIND_R2R) {
+            even = quad = true;
+            for (int s = 0; s < 2 && (even || quad); s++) {
+                const Layout &L = *S[s];
+                const int64_t npos = L.shape[a];
+                const int d = L.axis_dir[a];
+                const int64_t R = d < 0 ? 0 : L.rstride[d];
+                if (npos % 2) even = false;
+                if (npos % 4) quad = false;
+                for (int64_t j = 0; j < npos && (even || quad); j++) {
+                    const int64_t c = L.own[a][j], loc = L.loc[a][j];
+                    const int64_t na = L.local_extent(a, c);
+                    const int64_t addr = L.rank_off[t.rank[s] + c * R] + ((int64_t)t.O[s] * na + loc) * t.E[s] + t.I[s];
+                    const int64_t lstride = na * t.E[s];
+                    if (j % 2 == 0 && ((addr & 1) || (lstride & 1) || j + 1 >= npos || L.own[a][j + 1] != c))
+                        even = false;
+                    if (j % 4 == 0 && ((addr & 3) || (lstride & 3) || j + 3 >= npos || L.own[a][j + 3] != c))
+                        quad = false;
+                }
+            }
+        }
+        if (t.run > 0) {
+            even = even && (t.run % 2 == 0) && (t.b0 % 2 == 0) && (t.ostr[0] % 2 == 0) && (t.ostr[1] % 2 == 0);
+            quad = quad && (t.run % 4 == 0) && (t.b0 % 4 == 0) && (t.ostr[0] % 4 == 0) && (t.ostr[1] % 4 == 0);
+        }
+        for (int s = 0; s < 2 && !contig && (even || quad); s++) {
             const Layout &L = *S[s];
             const int64_t npos = L.shape[a];
             const int d = L.axis_dir[a];
             const int64_t R = d < 0 ? 0 : L.rstride[d];
             const int64_t first = t.run > 0 ? t.b0 : 0;  // element offset of line 0 from (O, I)
-            for (int64_t j = 0; j < npos && even; j++) {
+            for (int64_t j = 0; j < npos && (even || quad); j++) {
                 const int64_t c = L.own[a][j], loc = L.loc[a][j];
                 const int64_t na = L.local_extent(a, c);
                 const int64_t addr =
                     L.rank_off[t.rank[s] + c * R] + ((int64_t)t.O[s] * na + loc) * t.E[s] + t.I[s] + first;
                 if (addr & 1) even = false;
+                if (addr & 3) quad = false;
             }
         }
-        t.flags = even ? 1 : 0;
+        t.flags = (even ? 1 : 0) | (quad ? 2 : 0);
         tiles.push_back(t);
     }
     ln.ntiles = (int64_t)tiles.size();
