@@ -44,8 +44,12 @@
  * to every call.  All transform calls are asynchronous on the given stream,
  * out-of-place, never write their input, and make no host synchronisation;
  * they may be captured into a HIP graph.  Pointers are device pointers unless
- * stated otherwise.  A plan is immutable after binding; calls on different
- * streams may share a plan if each call has its own output and workspace.
+ * stated otherwise; the input, output and workspace buffers of the transform
+ * calls and batches must be 16-byte aligned (PFFT_EINVAL otherwise: kernels
+ * move 16-byte pieces at offsets the plan checked from the buffers' starts;
+ * hipMalloc and torch allocations are).  A plan is immutable after binding;
+ * calls on different streams may share a plan if each call has its own output
+ * and workspace.
  *
  * Errors.  Every function returns an int status: PFFT_OK (0) or a negative
  * code below.  No function aborts or throws.  pfft_strerror() names a code.

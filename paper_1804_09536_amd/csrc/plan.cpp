@@ -956,6 +956,10 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
     if (p->flags & PFFT_LAYOUTS_ONLY) return fail(PFFT_EUNSUPPORTED, "plan was created with PFFT_LAYOUTS_ONLY");
     if (!p->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     if (!in || !out) return fail(PFFT_EINVAL, "null buffer");
+    // full aligned tiles move 16-byte pieces at offsets the plan checked
+    // relative to the buffers' starts
+    if (((uintptr_t)in | (uintptr_t)out | (uintptr_t)work) & 15u)
+        return fail(PFFT_EINVAL, "in, out and work must be 16-byte aligned");
     const int n = (int)list.size();
     std::vector<const void *> srcs;
     std::vector<void *> dsts;
@@ -1590,6 +1594,8 @@ int pfft_batch_bind(pfft_batch b, void *state, void *in, void *out, void *work, 
     PFFT_GUARD_BEGIN
     if (!b || !state || !in || !out || !work) return fail(PFFT_EINVAL, "null argument");
     if (((uintptr_t)state & 255u) != 0) return fail(PFFT_EINVAL, "device state must be 256-byte aligned");
+    if (((uintptr_t)in | (uintptr_t)out | (uintptr_t)work) & 15u)
+        return fail(PFFT_EINVAL, "in, out and work must be 16-byte aligned");
     b->dev = state;
     b->in = in;
     b->out = out;

@@ -185,3 +185,19 @@ def test_destroy_input_gives_identical_results(shape, grid, kind, placement, pat
     assert back.tobytes() == ref_b.tobytes()
     if dest.workspace_bytes() == 0:
         assert dest.workspace() is None
+
+
+def test_misaligned_buffers_are_refused():
+    # full tiles move 16-byte pieces at offsets checked from the buffers'
+    # starts: a buffer that starts 8 bytes into an allocation is refused
+    from paper_1804_09536_amd._lib import PfftError
+    p = Plan((16, 8, 32), (2, 2))
+    n, m = p.buffer_numel(0), p.buffer_numel(p.num_layouts - 1)
+    big = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    with pytest.raises(PfftError):
+        p.forward(big[1:])                       # misaligned input
+    out = torch.zeros(m + 1, dtype=torch.complex64, device="cuda")
+    with pytest.raises(PfftError):
+        p.forward(big[:n], out=out[1:])          # misaligned output
+    torch.cuda.synchronize()
+    assert out.abs().sum().item() == 0.0         # nothing ran
