@@ -130,6 +130,19 @@ struct R2RLines {
     static constexpr int FLAG = RW::FLAG;
 };
 
+// Tile of workgroup b when the device hands workgroups to its 8 XCDs in turn
+// (b to XCD b % 8): each XCD takes one contiguous range of tiles, in order, so
+// neighbouring tiles that share cache lines meet in the same L2.  (A bijection
+// of 0..n-1 for any n, so only the traffic depends on the dispatch order.)
+// Strided real tiles of 16 lines have 64-byte rows: two tiles share every
+// 128-byte line, which round-robin order fetched twice from two L2s.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    constexpr int X = 8;
+    const int q = n / X, r = n % X, x = b % X, k = b / X;
+    return x * q + (x < r ? x : r) + k;
+}
+
 template <typename T, int N, bool CONTIG, class S>
 __global__ __launch_bounds__(S::NT) void k_r2r(StageArgs a, const Tile *__restrict__ tiles)
 {
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__r
     int wl[NL];
 #pragma unroll
     for (int l = 0; l < NL; l++) wl[l] = slot + l * SLOTS;
-    const Tile &t = tiles[blockIdx.x];
+    const Tile &t = tiles[CONTIG ? (int)blockIdx.x : xcd_tile(blockIdx.x, (int)a.ntiles)];
     const int count = t.count;
     const bool inverse = (a.flags & SF_R2R_INVERSE) != 0;
     const bool sine = (a.flags & SF_R2R_SINE) != 0;
