@@ -114,9 +114,6 @@ struct R2RRows<float, N, W, NT, CONTIG> {
 // tid % CPL of lines tid / CPL + i * LG, i < LPT.  Used for full tiles whose
 // aligned groups of Q positions are adjacent and start at a multiple of Q
 // elements in every line on both sides (tile flag FLAG).
-#ifndef PFFT_R2R_WIDE_CONTIG
-#define PFFT_R2R_WIDE_CONTIG 1
-#endif
 template <typename T, int N, int W, int NT, bool CONTIG>
 struct R2RLines {
     using RW = R2RRows<T, N, W, NT, false>;  // piece type and accessors
@@ -125,8 +122,7 @@ struct R2RLines {
     static constexpr int CPL = N / Q > 0 ? N / Q : 1;
     static constexpr int LG = NT / CPL > 0 ? NT / CPL : 1;
     static constexpr int LPT = W / LG > 0 ? W / LG : 1;
-    static constexpr bool on = PFFT_R2R_WIDE_CONTIG && CONTIG && N % Q == 0 && CPL <= NT && NT % CPL == 0 &&
-                               W % LG == 0 && LPT <= 32;
+    static constexpr bool on = CONTIG && N % Q == 0 && CPL <= NT && NT % CPL == 0 && W % LG == 0 && LPT <= 32;
     static constexpr int FLAG = RW::FLAG;
 };
 
