@@ -315,6 +315,30 @@ typedef struct {
 int pfft_set_profiling(pfft_plan plan, int enable);
 int pfft_profile_read(pfft_plan plan, int max_entries, pfft_profile_entry *entries, int *n);
 
+/*
+ * Weighted spectral energy, the quadratic loss of the differentiation
+ * workload (not part of the paper's method: it exercises the adjoint
+ * transforms, with w = |k|^2 on the forward output):
+ *   loss[0] = sum_i w_i |u_i|^2  over n complex elements u (complex64 for
+ *   PFFT_F32, complex128 for PFFT_F64) with real weights w of the same
+ *   precision; loss is one real of that precision on the device.
+ * Per-workgroup FP64 partial sums go to `partials` (caller scratch of
+ * PFFT_ENERGY_PARTIALS doubles), then are added in a fixed order, so the
+ * result does not depend on scheduling.  Asynchronous on `stream`; buffers
+ * naturally aligned for their element types.  n = 0 gives 0.
+ */
+#define PFFT_ENERGY_PARTIALS 1024
+int pfft_weighted_energy(int precision, int64_t n, const void *u, const void *w, double *partials, void *loss,
+                         hipStream_t stream);
+
+/*
+ * Its gradient under torch's convention for complex inputs:
+ *   grad_i = 2 g w_i u_i,  g = *g_dev (one real of the precision, on the
+ * device: the incoming gradient of the loss).  grad may not overlap u.
+ */
+int pfft_weighted_energy_grad(int precision, int64_t n, const void *u, const void *w, const void *g_dev,
+                              void *grad, hipStream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char *pfft_strerror(int status);
 

@@ -20,6 +20,7 @@ PATHS = {"fused": 0, "unfused": 1, "pack_realign": 2}
 PFFT_LAYOUTS_ONLY = 4
 PFFT_PLACE_SCATTER = 8
 PFFT_DESTROY_INPUT = 1 << 8
+ENERGY_PARTIALS = 1024  # PFFT_ENERGY_PARTIALS: FP64 scratch of pfft_weighted_energy
 PLACEMENTS = {"gather": 0, "scatter": 1, "direct": 2, "final": 3}
 
 _lib = None
@@ -83,6 +84,8 @@ def load():
         "pfft_backward": [vp, vp, vp, vp, vp],
         "pfft_adjoint_forward": [vp, vp, vp, vp, vp],
         "pfft_adjoint_backward": [vp, vp, vp, vp, vp],
+        "pfft_weighted_energy": [c_int, ctypes.c_int64, vp, vp, vp, vp, vp],
+        "pfft_weighted_energy_grad": [c_int, ctypes.c_int64, vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)

@@ -11,7 +11,9 @@ from __future__ import annotations
 
 import torch
 
-from .plan import Plan
+from . import _lib
+from ._lib import check
+from .plan import Plan, _ptr, _stream_handle
 
 
 class _Forward(torch.autograd.Function):
@@ -74,24 +76,46 @@ def global_indices(plan: Plan, layout: int, real: bool = False, device=None):
     return [torch.cat(p).to(device) for p in parts]
 
 
+_ENERGY = {torch.complex64: (0, torch.float32), torch.complex128: (1, torch.float64)}
+
+
+def _energy_args(uh, w):
+    if uh.dtype not in _ENERGY:
+        raise TypeError("expected complex64 or complex128, got %s" % uh.dtype)
+    prec, rdt = _ENERGY[uh.dtype]
+    if w.dtype != rdt or w.numel() != uh.numel() or not (uh.is_cuda and w.is_cuda):
+        raise ValueError("the weight must be a %s device tensor with one value per element" % rdt)
+    return prec, rdt, uh.contiguous(), w.contiguous()
+
+
 class _WeightedEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, uh, w):
-        wu = w * uh
-        ctx.save_for_backward(wu)
-        return torch.vdot(uh, wu).real
+        prec, rdt, uh, w = _energy_args(uh, w)
+        lib = _lib.load()
+        partials = torch.empty(_lib.ENERGY_PARTIALS, dtype=torch.float64, device=uh.device)
+        loss = torch.empty((), dtype=rdt, device=uh.device)
+        check(lib.pfft_weighted_energy(prec, uh.numel(), _ptr(uh), _ptr(w), _ptr(partials), _ptr(loss),
+                                       _stream_handle(uh.device)), "pfft_weighted_energy")
+        ctx.prec = prec
+        ctx.save_for_backward(uh, w)
+        return loss
 
     @staticmethod
     def backward(ctx, g):
-        (wu,) = ctx.saved_tensors
-        return wu * (2 * g), None
+        uh, w = ctx.saved_tensors
+        g = g.to(w.dtype).contiguous()
+        grad = torch.empty_like(uh)
+        check(_lib.load().pfft_weighted_energy_grad(ctx.prec, uh.numel(), _ptr(uh), _ptr(w), _ptr(g), _ptr(grad),
+                                                    _stream_handle(uh.device)), "pfft_weighted_energy_grad")
+        return grad, None
 
 
 def weighted_energy(uh: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
-    """sum_k w(k) |uh(k)|^2 for a real weight w on the same buffer, with its
-    gradient 2 w uh (torch's convention for complex inputs) formed in one
-    pass: the loss of the differentiation workload without the chain of
-    elementwise kernels autograd would record for it."""
+    """sum_k w(k) |uh(k)|^2 for a real weight w (the real type of uh) on the
+    same buffer, and its gradient 2 w uh (torch's convention for complex
+    inputs), each in one pass of the library's kernels (pfft_weighted_energy,
+    pfft_weighted_energy_grad): the loss of the differentiation workload."""
     return _WeightedEnergy.apply(uh, w)
 
 

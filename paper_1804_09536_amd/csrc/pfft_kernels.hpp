@@ -54,4 +54,12 @@ hipError_t r2r_launch_f64(int N, int contig, const KernelConfig &cfg, const Stag
 // N-point transform (the N-point and 4N-point tables).
 bool r2r_half_length(int N);
 
+// Weighted energy sum_i w_i |u_i|^2 of n complex elements into loss[0] (the
+// precision's real type), through kEnergyPartials FP64 partial sums; and its
+// gradient grad_i = 2 g[0] w_i u_i.
+constexpr int kEnergyPartials = 1024;
+hipError_t energy_launch(int prec, long n, const void *u, const void *w, double *partials, void *loss, hipStream_t s);
+hipError_t energy_grad_launch(int prec, long n, const void *u, const void *w, const void *g, void *grad,
+                              hipStream_t s);
+
 }  // namespace pfft

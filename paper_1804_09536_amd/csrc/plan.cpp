@@ -1582,6 +1582,49 @@ int pfft_batch_member_offsets(pfft_batch b, int member, size_t *in_offset, size_
     return PFFT_OK;
 }
 
+static_assert(PFFT_ENERGY_PARTIALS == pfft::kEnergyPartials, "partials buffer size");
+
+// x: always needed (partials / the gradient scalar); y: the loss (always) or
+// the gradient (when n > 0)
+static int energy_args(int precision, int64_t n, const void *u, const void *w, const void *x, const void *y,
+                       size_t xalign, size_t yalign, bool y_always)
+{
+    if (precision != PFFT_F32 && precision != PFFT_F64) return fail(PFFT_EDTYPE, "bad precision");
+    if (n < 0) return fail(PFFT_EINVAL, "negative element count");
+    if (!x || (!y && (y_always || n > 0)) || (n > 0 && (!u || !w))) return fail(PFFT_EINVAL, "null buffer");
+    const uintptr_t r = precision == PFFT_F32 ? 4 : 8;
+    if (((uintptr_t)u % (2 * r)) || ((uintptr_t)w % r) || ((uintptr_t)x % xalign) || ((uintptr_t)y % yalign))
+        return fail(PFFT_EINVAL, "misaligned buffer");
+    return PFFT_OK;
+}
+
+int pfft_weighted_energy(int precision, int64_t n, const void *u, const void *w, double *partials, void *loss,
+                         hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    const size_t r = precision == PFFT_F64 ? 8 : 4;
+    int rc = energy_args(precision, n, u, w, partials, loss, 8, r, true);
+    if (rc) return rc;
+    hipError_t e = energy_launch(precision == PFFT_F64 ? 1 : 0, (long)n, u, w, partials, loss, stream);
+    if (e != hipSuccess) return fail(PFFT_EHIP, std::string("energy launch: ") + hipGetErrorString(e));
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
+int pfft_weighted_energy_grad(int precision, int64_t n, const void *u, const void *w, const void *g_dev, void *grad,
+                              hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    const size_t r = precision == PFFT_F64 ? 8 : 4;
+    int rc = energy_args(precision, n, u, w, g_dev, grad, r, 2 * r, false);
+    if (rc) return rc;
+    if (n > 0 && grad == u) return fail(PFFT_EINVAL, "grad overlaps u");
+    hipError_t e = energy_grad_launch(precision == PFFT_F64 ? 1 : 0, (long)n, u, w, g_dev, grad, stream);
+    if (e != hipSuccess) return fail(PFFT_EHIP, std::string("energy gradient launch: ") + hipGetErrorString(e));
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
 int pfft_batch_device_state_bytes(pfft_batch b, size_t *bytes)
 {
     if (!b || !bytes) return fail(PFFT_EINVAL, "null argument");

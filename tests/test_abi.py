@@ -150,3 +150,17 @@ def test_buffers_of_2_31_elements_are_refused():
     # kernels address buffers with 32-bit element offsets: 2^31 elements is one too many
     assert _create((2048, 1024, 1024), (8, 8)) == -5
     assert _create((1536, 1024, 1024), (8, 8), flags=4) == 0
+
+
+def test_weighted_energy_argument_checks():
+    # checked before anything is launched, so no device is needed
+    lib = _lib.load()
+    v = ctypes.c_void_p
+    a16, a8 = v(4096), v(4104)   # stand-in addresses: 16-byte and 8-byte aligned
+    assert lib.pfft_weighted_energy(2, 4, a16, a16, a16, a16, None) == -4       # bad precision
+    assert lib.pfft_weighted_energy(0, -1, a16, a16, a16, a16, None) == -1      # negative count
+    assert lib.pfft_weighted_energy(0, 4, None, a16, a16, a16, None) == -1      # null input
+    assert lib.pfft_weighted_energy(0, 4, a16, a16, None, a16, None) == -1      # null partials
+    assert lib.pfft_weighted_energy(1, 4, a8, a16, a16, a16, None) == -1        # complex128 needs 16 bytes
+    assert lib.pfft_weighted_energy_grad(0, 4, a16, a16, a16, a16, None) == -1  # grad overlaps u
+    assert lib.pfft_weighted_energy_grad(0, 4, a16, a16, None, a8, None) == -1  # null gradient scalar

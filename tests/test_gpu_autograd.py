@@ -80,3 +80,27 @@ def test_gradient_256cubed_matches_oracle(fused):
     eloss, egrad = oracle.loss_and_grad(ch, u0.astype(np.float64), wg)
     assert abs(float(loss) - eloss) <= 1e-5 * abs(eloss)
     assert np.linalg.norm(g - egrad) / np.linalg.norm(egrad) <= 1e-5
+
+
+@pytest.mark.parametrize("n,prec", [(0, "f32"), (1, "f64"), (1000, "f32"), (300_001, "f64"), (1_000_003, "f32")])
+def test_weighted_energy_kernels_match_fp64(n, prec):
+    # loss = sum w |u|^2 (FP64 partial sums, fixed order: bitwise repeatable)
+    # and grad = 2 g w u, against numpy in FP64, on counts that leave a
+    # ragged last workgroup and more workgroups than partial sums
+    print("case", n, prec, flush=True)
+    cdt, rdt = (np.complex64, np.float32) if prec == "f32" else (np.complex128, np.float64)
+    u0 = inputs.uniform_complex(max(n, 1), [31, n], cdt)[:n]
+    w0 = np.abs(inputs.gaussian_real(max(n, 1), [32, n], rdt))[:n]
+    u = torch.from_numpy(u0).cuda().requires_grad_()
+    w = torch.from_numpy(w0).cuda()
+    loss = pad.weighted_energy(u, w)
+    again = pad.weighted_energy(u.detach(), w)
+    assert loss.item() == again.item()
+    expect = float(np.sum(w0.astype(np.float64) * np.abs(u0.astype(np.complex128)) ** 2))
+    tol = 1e-6 if prec == "f32" else 1e-13
+    assert abs(loss.item() - expect) <= tol * max(abs(expect), 1e-30)
+    (3.0 * loss).backward()
+    g = u.grad.cpu().numpy()
+    eg = 6.0 * w0.astype(np.float64) * u0.astype(np.complex128)
+    if n:
+        assert np.linalg.norm(g - eg) <= (1e-6 if prec == "f32" else 1e-14) * np.linalg.norm(eg)
