@@ -998,9 +998,12 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
         na[s] = (const int32_t *)(p->blob.data() + ln.off_na[s]);
         roff[s] = (const int64_t *)(p->blob.data() + ln.off_rank[s]);
     }
+    std::vector<int64_t> ad;  // the tile's addresses, (line, position, side)
     for (int64_t ti = 0; ti < ln.ntiles; ti++) {
         const Tile &t = tiles[ti];
         if (t.count < 1 || t.count > ln.cfg.W) return fail(PFFT_EINTERNAL, std::string(what) + ": tile count");
+        const int64_t jall = std::max(npos[0], npos[1]);
+        ad.assign((size_t)t.count * (size_t)jall * 2, -1);
         if (t.run < 0 || (t.run > 0 && (ln.contig || t.b0 < 0 || t.b0 >= t.run)))
             return fail(PFFT_EINTERNAL, std::string(what) + ": tile run");
         for (int w = 0; w < t.count; w++) {
@@ -1029,6 +1032,7 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
                         I += w;
                     }
                     addr[s] = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
+                    ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s] = addr[s];
                     if (I < 0 || I >= t.E[s] || addr[s] < roff[s][rank] || addr[s] >= roff[s][rank + 1] ||
                         addr[s] >= size[s])
                         return fail(PFFT_EINTERNAL, std::string(what) + ": address out of its block");
@@ -1048,6 +1052,26 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
                         return fail(PFFT_EINTERNAL, std::string(what) + ": position");
                 }
             }
+        }
+        // the alignment flags promise groups of G adjacent elements starting
+        // at a multiple of G: lines 2i.. (strided) or positions 2i.. of every
+        // line (contiguous), G = 2 (bit 0) or 4 (bit 1), on both sides
+        for (int bit = 0; bit < 2; bit++) {
+            if (!(t.flags & (1 << bit))) continue;
+            const int64_t G = bit == 0 ? 2 : 4;
+            for (int s = 0; s < 2; s++)
+                for (int w = 0; w < t.count; w++)
+                    for (int64_t j = 0; j < npos[s]; j++) {
+                        const bool first = ln.contig ? (j % G == 0) : (w % G == 0 && w + G <= t.count);
+                        if (!first) continue;
+                        const int64_t a0 = ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s];
+                        bool ok = a0 % G == 0 && (!ln.contig || j + G <= npos[s]);
+                        for (int64_t k = 1; k < G && ok; k++) {
+                            const int64_t wk = ln.contig ? w : w + k, jk = ln.contig ? j + k : j;
+                            ok = ad[((size_t)wk * (size_t)jall + (size_t)jk) * 2 + (size_t)s] == a0 + k;
+                        }
+                        if (!ok) return fail(PFFT_EINTERNAL, std::string(what) + ": tile alignment flag");
+                    }
         }
     }
     for (int64_t e = 0; e < size[1]; e++)
