@@ -274,7 +274,16 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     T2 v[NL][P];
     SideAddr<P> d;
     int c;
-    for (long ti = blockIdx.x; ti < nt; ti += G) {
+    // SF_XCD_ORDER with one tile per workgroup: workgroup b runs on XCD
+    // b % 8, which takes the contiguous range x*q + min(x, r) + [0, q + (x < r))
+    // of the nt = 8q + r tiles (a bijection of the tile indices)
+    const bool xcd = !CONTIG && (a.flags & SF_XCD_ORDER) && G == nt;
+    for (long ti0 = blockIdx.x; ti0 < nt; ti0 += G) {
+        long ti = ti0;
+        if (xcd) {
+            const long q = nt / 8, r = nt % 8, x = ti0 % 8, k = ti0 / 8;
+            ti = x * q + (x < r ? x : r) + k;
+        }
         wk.refresh();
         // (contiguous stages measured faster with the tile read through the
         // vector path)

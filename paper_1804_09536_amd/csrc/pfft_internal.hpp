@@ -68,6 +68,8 @@ enum StageFlags : int32_t {
     SF_R2R_SINE = 8,         // R2R: sine instead of cosine transform
     SF_R2R_ADJOINT = 16,     // R2R: the transpose of the transform (type III: special input
                              // element doubled; type II: special output element halved)
+    SF_XCD_ORDER = 32,       // complex strided stage, one tile per workgroup: each of the 8 XCDs
+                             // (workgroup b runs on XCD b % 8) takes one contiguous range of tiles
 };
 
 struct StageArgs {

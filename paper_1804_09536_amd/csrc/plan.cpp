@@ -161,6 +161,7 @@ struct Launch {
     int sign = -1;
     int scale_axis = -1;   // axis whose 1/N_m factor may apply (-1: none)
     int sine = 0;          // R2R: sine (1) or cosine (0) transform
+    int xcd = 0;           // complex strided stage whose tiles go to the XCDs in contiguous ranges
     // device blob offsets
     size_t off_tiles = 0;
     int64_t ntiles = 0;
@@ -516,6 +517,14 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
     }
     ln.ntiles = (int64_t)tiles.size();
     ln.off_tiles = blob_put(p, tiles.data(), tiles.size() * sizeof(Tile));
+    // A complex strided stage that stores straight into a layout splitting its
+    // axis (rows of a tile scattered over the blocks of that direction) with
+    // unwrapped tiles: neighbouring tiles complete each other's row segments,
+    // so they are kept in one XCD's L2 (measured -6 % on such a 512^3 stage;
+    // gathering stages and wrapped tiles measured slower and keep the order).
+    bool wrapped = false;
+    for (const Tile &t : tiles) wrapped = wrapped || t.run > 0;
+    ln.xcd = (ln.kind == KIND_C2C && !contig && B.axis_dir[a] >= 0 && !wrapped) ? 1 : 0;
 }
 
 static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs)
@@ -860,7 +869,7 @@ static int stage_flags(const Launch &ln, int sign, int chain_flags)
         return (sign > 0 ? SF_R2R_INVERSE : 0) | (ln.sine ? SF_R2R_SINE : 0) |
                ((chain_flags & (SF_HALVE_INTERIOR | SF_DOUBLE_INTERIOR)) ? SF_R2R_ADJOINT : 0);
     if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) return chain_flags;
-    return 0;
+    return ln.xcd ? SF_XCD_ORDER : 0;
 }
 
 static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
