@@ -521,10 +521,11 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
     // axis (rows of a tile scattered over the blocks of that direction) with
     // unwrapped tiles: neighbouring tiles complete each other's row segments,
     // so they are kept in one XCD's L2 (measured -6 % on such a 512^3 stage;
-    // gathering stages and wrapped tiles measured slower and keep the order).
+    // gathering stages, wrapped tiles and the one-workgroup-per-CU tiles of
+    // 1024 points and more measured slower and keep the order).
     bool wrapped = false;
     for (const Tile &t : tiles) wrapped = wrapped || t.run > 0;
-    ln.xcd = (ln.kind == KIND_C2C && !contig && B.axis_dir[a] >= 0 && !wrapped) ? 1 : 0;
+    ln.xcd = (ln.kind == KIND_C2C && !contig && B.axis_dir[a] >= 0 && !wrapped && ln.N <= 512) ? 1 : 0;
 }
 
 static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs)
