@@ -520,12 +520,17 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
     // A complex strided stage that stores straight into a layout splitting its
     // axis (rows of a tile scattered over the blocks of that direction) with
     // unwrapped tiles: neighbouring tiles complete each other's row segments,
-    // so they are kept in one XCD's L2 (measured -6 % on such a 512^3 stage;
-    // gathering stages, wrapped tiles and the one-workgroup-per-CU tiles of
-    // 1024 points and more measured slower and keep the order).
+    // so they are kept in one XCD's L2 (measured -6 % on such a 512^3 stage).
+    // Gathering stages, wrapped tiles, the one-workgroup-per-CU tiles of 1024
+    // points and more, and buffers that fit the 256 MB last-level cache (whose
+    // writes stay there: 256^3 measured 2 % slower) keep the round-robin order.
     bool wrapped = false;
     for (const Tile &t : tiles) wrapped = wrapped || t.run > 0;
-    ln.xcd = (ln.kind == KIND_C2C && !contig && B.axis_dir[a] >= 0 && !wrapped && ln.N <= 512) ? 1 : 0;
+    const double dst_bytes = (double)B.total() * (p->precision == PFFT_F32 ? 8.0 : 16.0);
+    ln.xcd = (ln.kind == KIND_C2C && !contig && B.axis_dir[a] >= 0 && !wrapped && ln.N <= 512 &&
+              dst_bytes > 256.0 * 1048576.0)
+                 ? 1
+                 : 0;
 }
 
 static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs)
