@@ -296,11 +296,67 @@ static void twiddle(int64_t m, int64_t n, int sign, double *re, double *im)
     *im = (double)sign * sin(a);
 }
 
+/* Smallest prime factor of n >= 2 (n itself when n is prime). */
+static int64_t smallest_factor(int64_t n)
+{
+    for (int64_t f = 2; f * f <= n; f++)
+        if (n % f == 0) return f;
+    return n;
+}
+
+/*
+ * Mixed-radix decimation in time (the Cooley-Tukey factorisation of Eq. 1):
+ * with n = p * m, p the smallest prime factor of n, the p subsequences
+ * x_{r + p j} (j < m) are transformed with length m into Y_r, and then
+ *   y_k = sum_{r<p} e^{sign 2 pi i r k / n} Y_r[k mod m],  k < n.
+ * Prime lengths are the direct sum of Eq. 1.  x is read with a stride of
+ * `xs` complex elements; y receives n contiguous results.  tw holds
+ * e^{sign 2 pi i t / ntw} for t < ntw (n divides ntw), so the factor of
+ * exponent r k / n is tw[(r k mod n) * (ntw / n)]; work holds n complex.
+ */
+static void dft_mixed(const double *x, int64_t xs, double *y, int64_t n, const double *tw, int64_t ntw,
+                      double *work)
+{
+    const int64_t step = ntw / n;
+    const int64_t p = n > 1 ? smallest_factor(n) : 1;
+    if (p == n) {
+        for (int64_t k = 0; k < n; k++) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t j = 0; j < n; j++) {
+                const double *w = tw + 2 * (((j * k) % n) * step);
+                const double *u = x + 2 * j * xs;
+                sr += u[0] * w[0] - u[1] * w[1];
+                si += u[0] * w[1] + u[1] * w[0];
+            }
+            y[2 * k] = sr;
+            y[2 * k + 1] = si;
+        }
+        return;
+    }
+    const int64_t m = n / p;
+    /* Y_r into y[r m .. (r+1) m) (each sub-transform uses work only before
+       this level's combination below) */
+    for (int64_t r = 0; r < p; r++) dft_mixed(x + 2 * r * xs, xs * p, y + 2 * r * m, m, tw, ntw, work);
+    for (int64_t k = 0; k < n; k++) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t r = 0; r < p; r++) {
+            const double *w = tw + 2 * (((r * k) % n) * step);
+            const double *u = y + 2 * (r * m + k % m);
+            sr += u[0] * w[0] - u[1] * w[1];
+            si += u[0] * w[1] + u[1] * w[0];
+        }
+        work[2 * k] = sr;
+        work[2 * k + 1] = si;
+    }
+    memcpy(y, work, (size_t)(2 * n) * sizeof(double));
+}
+
 /*
  * Unnormalised 1-D DFT of x (n complex, interleaved), result into y:
  *   y_k = sum_j x_j e^{sign 2 pi i jk/n}.
  * Powers of two use an iterative radix-2 decimation-in-time FFT (bit-reversal
- * permutation, then log2 n butterfly passes); other lengths the direct sum.
+ * permutation, then log2 n butterfly passes); other composite lengths the
+ * mixed-radix recursion above; primes the direct sum.
  */
 static void dft1(const double *x, double *y, int64_t n, int sign)
 {
@@ -332,17 +388,12 @@ static void dft1(const double *x, double *y, int64_t n, int sign)
             }
         }
     } else {
-        for (int64_t k = 0; k < n; k++) {
-            double sr = 0.0, si = 0.0;
-            for (int64_t j = 0; j < n; j++) {
-                double wr, wi;
-                twiddle((j * k) % n, n, sign, &wr, &wi);
-                sr += x[2 * j] * wr - x[2 * j + 1] * wi;
-                si += x[2 * j] * wi + x[2 * j + 1] * wr;
-            }
-            y[2 * k] = sr;
-            y[2 * k + 1] = si;
-        }
+        double *tw = (double *)malloc((size_t)(2 * n) * sizeof(double));
+        double *work = (double *)malloc((size_t)(2 * n) * sizeof(double));
+        for (int64_t t = 0; t < n; t++) twiddle(t, n, sign, &tw[2 * t], &tw[2 * t + 1]);
+        dft_mixed(x, 1, y, n, tw, n, work);
+        free(tw);
+        free(work);
     }
 }
 

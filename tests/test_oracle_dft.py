@@ -23,11 +23,26 @@ def _direct_line(x, sign):
     return np.array(out)
 
 
-@pytest.mark.parametrize("n", list(range(1, 21)) + [32, 64])
+# composite lengths run the mixed-radix recursion (factors 2, 3, 5, 7, 11 and
+# their products, several levels deep), primes the direct sum, powers of two
+# the radix-2 passes
+@pytest.mark.parametrize("n", list(range(1, 21)) + [21, 24, 25, 27, 30, 32, 35, 36, 45, 48, 49, 55, 63, 64, 77,
+                                                    96, 105, 121])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_dft1_equals_direct_sum(n, sign):
     x = inputs.uniform_complex(n, [10, n], np.complex128)
     assert np.allclose(oracle.dft1(x, sign), _direct_line(x, sign), rtol=0, atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("n", [192, 384, 768, 1000, 1536, 2048, 3072, 6144, 4099, 10247, 2 * 3 * 5 * 7 * 11])
+def test_dft1_long_lines_equal_numpy_fft(n):
+    # library special case: numpy's unnormalised fft / ifft are Eq. 1 and Eq. 2
+    # without the factor; rounding grows like log n (mixed radix, radix 2) or
+    # sqrt(n) (direct sum of a prime length)
+    x = inputs.uniform_complex(n, [13, n], np.complex128)
+    for sign, ref in ((-1, np.fft.fft(x)), (1, np.fft.ifft(x) * n)):
+        got = oracle.dft1(x, sign)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-13
 
 
 @pytest.mark.parametrize("shape", [(4, 6, 5), (3, 5, 7, 2), (2, 1, 8), (9,), (3, 4)])
