@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch events in the timed region")
     ap.add_argument("--placement", default=None,
                     help="gather|scatter|direct|final, or FWD,BWD (default: the library's default pair)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only: skip the FP64, real-input, 4-D, batch and autograd sub-benches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy one buffer of the workload's size with torch (a "
                          "known-size reference for hardware byte counters)")
@@ -86,6 +88,17 @@ def measured_traffic(kernel):
     return rec.get("traffic_bytes_per_launch", {}).get(kernel)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_name(rec):
     base = KIND_NAMES.get(rec["kind"], rec["kind"])
     mode = "contig" if rec["contig"] else "strided"
@@ -106,7 +119,8 @@ def cpu_baseline(shape, grid, kind, chain, u_np):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = {"value": round(dt * 1e3, 1), "unit": "ms per forward+backward", "cores": cores, "kind": "oracle",
-           "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)"}
+           "sample": "one full forward+backward of the same workload in FP64 (OpenMP over lines)",
+           "cpu_model": cpu_model()}
     # the same oracle on one thread, on a bounded sample: the 256^3 pencil on
     # 4x4 ranks, in a child process so that its OpenMP runtime starts with one thread
     import subprocess
@@ -138,10 +152,22 @@ BATCH_SHAPES = [
 ]
 
 
-def bench_batch(args):
+def _timeit(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_batch(steps, warmup):
     """168 complex64 transforms (7 shapes x 8 instances x 3 components): the
     batch (one launch per stage and kernel shape, captured in a HIP graph)
-    against one call per transform."""
+    against one call per transform.  Returns a record."""
     import torch
 
     from paper_1804_09536_amd import inputs
@@ -179,36 +205,37 @@ def bench_batch(args):
             batched()
     torch.cuda.synchronize()
 
-    def timeit(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / args.steps
+    t_graph = _timeit(graph.replay, steps, warmup)
+    t_batch = _timeit(batched, steps, warmup)
+    t_plain = _timeit(per_transform, steps, warmup)
+    # the same transforms one shape at a time: 24 calls of each plan
+    per_shape = {}
+    for p in uniq:
+        idx = [m for m, q in enumerate(members) if q is p]
 
-    t_graph = timeit(graph.replay)
-    t_batch = timeit(batched)
-    t_plain = timeit(per_transform)
-    out = {"metric": "fwd+bwd ms, 168 mixed complex64 transforms; batched vs per-transform",
-           "value": round(t_graph, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(t_graph, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "7 shapes x 8 instances x 3 components c2c complex64, mixed slab/pencil grids",
-                      "shapes": [[list(s), list(g)] for s, g in BATCH_SHAPES]},
-           "batched_graph_ms": round(t_graph, 3), "batched_eager_ms": round(t_batch, 3),
-           "per_transform_ms": round(t_plain, 3), "algorithmic_bytes": total_bytes,
-           "pct_hbm_peak": round(100.0 * total_bytes / (t_graph * 1e-3) / HBM_PEAK, 2)}
-    print(json.dumps(out), flush=True)
+        def shape_step(p=p, idx=idx):
+            for m in idx:
+                p.forward(batch.inputs[m], out=batch.outputs[m], work=work[id(p)])
+            for m in idx:
+                p.backward(batch.outputs[m], out=batch.inputs[m], work=work[id(p)])
+        per_shape["x".join(map(str, p.shape))] = round(_timeit(shape_step, steps, warmup), 3)
+    del graph, batch, work
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"workload": "7 shapes x 8 instances x 3 components c2c complex64, mixed slab/pencil grids",
+            "shapes": [[list(s), list(g)] for s, g in BATCH_SHAPES],
+            "batched_graph_ms": round(t_graph, 3), "batched_eager_ms": round(t_batch, 3),
+            "per_transform_ms": round(t_plain, 3), "per_shape_ms": per_shape,
+            "algorithmic_bytes": total_bytes,
+            "pct_hbm_peak": round(100.0 * total_bytes / (t_graph * 1e-3) / HBM_PEAK, 2),
+            "per_transform_pct_hbm_peak": round(100.0 * total_bytes / (t_plain * 1e-3) / HBM_PEAK, 2)}
 
 
-def bench_grad(args):
+def bench_grad(steps, warmup):
     """The differentiation workload: loss = sum_k |k|^2 |FFT(u)(k)|^2 on a
     256^3 float32 field (r2c, 4x4 pencil); one autograd step (forward, loss,
     backward through the adjoint kernels) against one plain forward+backward
-    of the same plan."""
+    of the same plan.  Returns a record."""
     import numpy as np
     import torch
 
@@ -236,57 +263,31 @@ def bench_grad(args):
         plan.forward(u0, out=y)
         plan.backward(y, out=z)
 
-    def timeit(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / args.steps
-
-    t_grad = timeit(grad_step)
-    t_plain = timeit(plain_step)
+    t_grad = _timeit(grad_step, steps, warmup)
+    t_plain = _timeit(plain_step, steps, warmup)
     spec = plan.buffer_numel(plan.num_layouts - 1) * 8
     real = plan.buffer_numel(0, real=True) * 4
     # r2c stage: real in + spectrum out; two complex stages: spectrum in + out; same for the adjoint
     step_bytes = 2 * ((real + spec) + 2 * (2 * spec))
-    out = {"metric": "autograd step (forward + loss + adjoint) vs plain fwd+bwd, 256^3 r2c float32",
-           "value": round(t_grad, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(t_grad, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "256x256x256 r2c float32, 4x4 pencil, loss sum |k|^2 |u_hat|^2"},
-           "autograd_step_ms": round(t_grad, 4), "plain_fwd_bwd_ms": round(t_plain, 4),
-           "transform_bytes_per_step": step_bytes}
-    print(json.dumps(out), flush=True)
+    return {"workload": "256x256x256 r2c float32, 4x4 pencil, loss sum |k|^2 |u_hat|^2",
+            "autograd_step_ms": round(t_grad, 4), "plain_fwd_bwd_ms": round(t_plain, 4),
+            "transform_bytes_per_step": step_bytes,
+            "plain_pct_hbm_peak": round(100.0 * step_bytes / (t_plain * 1e-3) / HBM_PEAK, 2)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the virtual ranks of the decomposition share one device; "
-              "run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def measure_plain(name, steps, warmup, path="fused", placement=None, profile=True, traffic=False):
+    """Forward+backward of one WORKLOADS entry: ms per step (mean over the
+    timed steps), per-launch HIP-event averages per kernel, the dominant
+    kernel's roofline record, and the round trip's relative error."""
     import numpy as np
     import torch
 
     from paper_1804_09536_amd import inputs
     from paper_1804_09536_amd.plan import Plan
 
-    if args.workload == "batch168":
-        bench_batch(args)
-        return
-    if args.workload == "grad256":
-        bench_grad(args)
-        return
-    shape, grid, kind, prec, chain = WORKLOADS[args.workload]
+    shape, grid, kind, prec, chain = WORKLOADS[name]
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    placement = tuple(args.placement.split(",")) if args.placement else None
-    if placement is not None and len(placement) == 1:
-        placement = placement * 2
-    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=args.path, device=dev,
+    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=path, device=dev,
                 placement=placement).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
     # arrays beyond 2^28 elements are drawn on the device (no host copy, no CPU baseline)
@@ -308,21 +309,21 @@ def main():
         plan.forward(x, out=y, work=work)
         plan.backward(y, out=z, work=work)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     plan.profile_read()
-    if not args.no_profile:
+    if profile:
         plan.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.set_profiling(False)
-    recs = plan.profile_read() if not args.no_profile else []
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    recs = plan.profile_read() if profile else []
+    ms_per_step = (t1 - t0) * 1e3 / steps
 
     # algorithmic bytes of one step: every launch of forward and backward
     step_bytes = 0.0
@@ -334,7 +335,7 @@ def main():
         d["n"] += 1
         d["bytes"] += r["bytes"]
         step_bytes += r["bytes"]
-    step_bytes /= max(1, args.steps)
+    step_bytes /= max(1, steps)
     roofline = None
     if per_kernel:
         dom = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
@@ -342,13 +343,68 @@ def main():
         avg_ms = d["ms"] / d["n"]
         per_launch = d["bytes"] / d["n"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(dom) if (args.workload == "pencil512" and args.placement is None
-                                            and args.path == "fused") else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": 8000.0,
-                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
+                    "traffic": measured_traffic(dom) if traffic else None,
                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": per_launch}
     # round-trip sanity on the last step
     rt = float(torch.linalg.vector_norm((z - x).flatten()) / torch.linalg.vector_norm(x.flatten()))
+    return {"plan": plan, "step": step, "x": x, "y": y, "u_np": u_np, "shape": shape, "grid": grid, "kind": kind,
+            "prec": prec, "chain": chain, "ms": ms_per_step, "step_bytes": step_bytes, "per_kernel": per_kernel,
+            "roofline": roofline, "roundtrip": rt}
+
+
+def plain_record(name, steps, warmup):
+    """A compact record of a WORKLOADS entry for the sub-benches of the default run."""
+    import torch
+    r = measure_plain(name, steps, warmup)
+    shape, grid, kind, prec = r["shape"], r["grid"], r["kind"], r["prec"]
+    out = {"workload": "%s %s %s on a %s virtual-rank grid" % ("x".join(map(str, shape)), kind,
+                                                              ("complex64" if prec == "f32" else "complex128")
+                                                              if kind != "r2c" else
+                                                              ("float32" if prec == "f32" else "float64"),
+                                                              "x".join(map(str, grid))),
+           "ms_per_step": round(r["ms"], 4), "step_bytes": r["step_bytes"],
+           "pct_hbm_peak": round(100.0 * r["step_bytes"] / (r["ms"] * 1e-3) / HBM_PEAK, 2),
+           "per_kernel_avg_ms": {k: round(v["ms"] / v["n"], 4) for k, v in r["per_kernel"].items()},
+           "roofline": r["roofline"], "roundtrip_rel_l2": r["roundtrip"]}
+    del r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the virtual ranks of the decomposition share one device; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.workload in ("batch168", "grad256"):
+        rec = bench_batch(args.steps, args.warmup) if args.workload == "batch168" else bench_grad(args.steps,
+                                                                                                     args.warmup)
+        ms = rec["batched_graph_ms"] if args.workload == "batch168" else rec["autograd_step_ms"]
+        metric = ("fwd+bwd ms, 168 mixed complex64 transforms; batched vs per-transform" if args.workload == "batch168"
+                  else "autograd step (forward + loss + adjoint) vs plain fwd+bwd, 256^3 r2c float32")
+        out = {"metric": metric, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic", "config": {"workload": rec["workload"]}}
+        out.update(rec)
+        print(json.dumps(out), flush=True)
+        return
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    placement = tuple(args.placement.split(",")) if args.placement else None
+    if placement is not None and len(placement) == 1:
+        placement = placement * 2
+    r = measure_plain(args.workload, args.steps, args.warmup, path=args.path, placement=placement,
+                      profile=not args.no_profile,
+                      traffic=(args.workload == "pencil512" and args.placement is None and args.path == "fused"))
+    plan, step, x, y = r["plan"], r["step"], r["x"], r["y"]
+    shape, grid, kind, prec, chain, u_np = r["shape"], r["grid"], r["kind"], r["prec"], r["chain"], r["u_np"]
+    ms_per_step, step_bytes, per_kernel, roofline = r["ms"], r["step_bytes"], r["per_kernel"], r["roofline"]
 
     # The paper's statistic (outside the timed region, Sec. 4): 50 blocks of 3
     # uninterrupted forward+backward pairs, each block bracketed by events on
@@ -391,10 +447,6 @@ def main():
         torch.cuda.synchronize()
         del ref
 
-    cpu = None
-    if not args.no_cpu_baseline and u_np is not None:
-        cpu = cpu_baseline(shape, grid, kind, chain, u_np)
-
     out = {
         "metric": "fwd+bwd 3D FFT ms & %HBM peak, 512^3 c2c FP32; batched/adjoint vs plain path",
         "value": round(ms_per_step, 4),
@@ -417,13 +469,38 @@ def main():
                    "placement": list(plan.placement), "tuning": plan.tuning()},
         "step_bytes": step_bytes,
         "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
-        "roundtrip_rel_l2": rt,
+        "roundtrip_rel_l2": r["roundtrip"],
         "per_kernel_avg_ms": {k: round(v["ms"] / v["n"], 4) for k, v in per_kernel.items()},
         "roofline": roofline,
         "paper_statistic": paper_stat,
         "copy_probe": copy_probe,
-        "cpu_baseline": cpu,
     }
+    del r, plan, step, x, y, src_c
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    # The metric's other half, measured in the same run on the same GPU: the
+    # paper's precision (FP64), the real-input and 4-D configurations, the
+    # batched form against per-transform calls and the autograd step against
+    # plain forward+backward.
+    if not args.no_extras and args.workload == "pencil512" and args.path == "fused" and args.placement is None:
+        xs, xw = max(5, min(args.steps, 10)), max(2, min(args.warmup, 3))
+        print("extras: fp64", file=sys.stderr, flush=True)
+        out["fp64"] = plain_record("pencil512_f64", xs, xw)
+        print("extras: r2c", file=sys.stderr, flush=True)
+        out["r2c"] = plain_record("r2c512", xs, xw)
+        print("extras: c2c4d", file=sys.stderr, flush=True)
+        out["c2c4d"] = plain_record("c2c4d64", xs, xw)
+        print("extras: batched", file=sys.stderr, flush=True)
+        out["batched"] = bench_batch(xs, xw)
+        print("extras: autograd", file=sys.stderr, flush=True)
+        out["autograd"] = bench_grad(xs, xw)
+
+    cpu = None
+    if not args.no_cpu_baseline and u_np is not None:
+        print("cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(shape, grid, kind, chain, u_np)
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -47,7 +47,8 @@
  * stated otherwise; the input, output and workspace buffers of the transform
  * calls and batches must be 16-byte aligned (PFFT_EINVAL otherwise: kernels
  * move 16-byte pieces at offsets the plan checked from the buffers' starts;
- * hipMalloc and torch allocations are).  A plan is immutable after binding;
+ * hipMalloc and torch allocations are), and must not overlap each other
+ * (PFFT_EINVAL otherwise).  A plan is immutable after binding;
  * calls on different streams may share a plan if each call has its own output
  * and workspace.
  *
@@ -173,7 +174,7 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * axis (tile_contig also to the real-to-complex and complex-to-real stages,
  * which have shapes 0 and 1 only), *_strided to the others.  Strided tiles
  * continue over consecutive short runs of lines (inner extents below the
- * tile width) where the blocks allow it.  pfft_plan_set_tuning rebuilds the plan's
+ * tile width) where the blocks allow it.  xcd_order: see the field.  pfft_plan_set_tuning rebuilds the plan's
  * tables: query pfft_device_state_bytes again and bind again before use.
  */
 typedef struct {
@@ -181,6 +182,11 @@ typedef struct {
     int tile_strided;
     int resident_contig;
     int resident_strided;
+    int xcd_order;  /* complex strided stages launched one tile per workgroup: 0 by the plan's rule
+                       (stages that store straight into a layout splitting their axis, unwrapped
+                       tiles, lines up to 512 points, destinations beyond 256 MiB), 1 always, 2 never.
+                       With it, each of the 8 XCDs (workgroup b runs on XCD b mod 8) takes one
+                       contiguous range of tiles. */
 } pfft_tuning;
 
 int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);

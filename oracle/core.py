@@ -563,9 +563,16 @@ def adjoint_backward(ch: Chain, buf: np.ndarray) -> np.ndarray:
     return _run_forward(ch, buf, -1, lambda a: ch.scale(a, "backward"), "r2c_double")
 
 
-def wavenumber_weight(spectral_shape, real_last: bool) -> np.ndarray:
+def wavenumber_weight(spectral_shape, real_last: bool, real_n: int = None, hermitian: bool = True) -> np.ndarray:
     """w(k) = |k|^2 with signed integer wavenumbers (numpy fftfreq * N) on the
-    full axes and 0..N/2 on the half axis of a real transform."""
+    full axes and 0..N/2 on the half axis of a real transform.
+
+    For a real transform (real_last) with ``hermitian`` set, every half-axis
+    bin k that stands for two bins of the full spectrum (k and real_n - k,
+    i.e. 0 < k < real_n - k) carries twice the weight, so that the weighted
+    sum over the stored half spectrum equals the sum over all k of the full
+    spectrum.  real_n is the real length of the last axis (default: the even
+    length 2 (h - 1) of a half axis of h bins)."""
     ks = []
     d = len(spectral_shape)
     for m, n in enumerate(spectral_shape):
@@ -574,12 +581,19 @@ def wavenumber_weight(spectral_shape, real_last: bool) -> np.ndarray:
         else:
             ks.append(np.fft.fftfreq(n, d=1.0 / n))
     grids = np.meshgrid(*ks, indexing="ij")
-    return sum(g * g for g in grids)
+    w = sum(g * g for g in grids)
+    if real_last and hermitian:
+        h = spectral_shape[-1]
+        rn = 2 * (h - 1) if real_n is None else int(real_n)
+        k = np.arange(h)
+        w = w * np.where((k > 0) & (k < rn - k), 2.0, 1.0)
+    return w
 
 
 def loss_and_grad(ch: Chain, u_layout0: np.ndarray, w_out_layout: np.ndarray):
     """L = sum_k w(k) |R u|^2 over the stored (half) spectrum, and its gradient
-    2 Re(R^H (w * R u)) in the input layout."""
+    2 Re(R^H (w * R u)) in the input layout (with the Hermitian weight of
+    ``wavenumber_weight``, L is the sum over the full spectrum)."""
     uh = forward(ch, u_layout0)
     loss = float(np.sum(w_out_layout * np.abs(uh) ** 2))
     grad = 2.0 * adjoint_forward(ch, w_out_layout * uh)

@@ -119,9 +119,13 @@ def weighted_energy(uh: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
     return _WeightedEnergy.apply(uh, w)
 
 
-def wavenumber_weight(plan: Plan, layout: int = -1) -> torch.Tensor:
+def wavenumber_weight(plan: Plan, layout: int = -1, hermitian: bool = True) -> torch.Tensor:
     """w(k) = |k|^2 on a (spectral) layout: signed integer wavenumbers on the
-    full axes, 0..N/2 on the half axis of a real-input plan."""
+    full axes, 0..N/2 on the half axis of a real-input plan.  For a real-input
+    plan with ``hermitian`` set, a half-axis bin k with 0 < k < N - k stands
+    for the two bins k and N - k of the full spectrum (equal magnitudes for a
+    real field, equal |k|^2) and carries twice the weight: the weighted energy
+    of the stored half spectrum is then the sum over the whole spectrum."""
     if layout < 0:
         layout = plan.num_layouts + layout
     idx = global_indices(plan, layout)
@@ -134,4 +138,7 @@ def wavenumber_weight(plan: Plan, layout: int = -1) -> torch.Tensor:
         if not (real and m == nd - 1):
             k = torch.where(k >= (n + 1) // 2, k - n, k)
         w += (k * k).to(torch.float64)
+    if real and hermitian:
+        n, k = plan.shape[-1], idx[-1]
+        w = torch.where((k > 0) & (k < n - k), 2.0 * w, w)
     return w

@@ -1,6 +1,7 @@
 """Build libpfft.so (HIP kernels for gfx950 + host plan engine) in-tree.
 
-Usage: ``python -m paper_1804_09536_amd.build`` or ``build()`` from Python.
+Usage: ``python -m paper_1804_09536_amd.build [--incremental]`` or ``build()``
+from Python.
 Every source is compiled with hipcc for gfx950 (packed-FP32 instructions off),
 in parallel, into ``_build/``; the shared library lands next to this file.
 """
@@ -8,6 +9,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -29,8 +31,30 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
+def _deps(path: str, seen=None) -> set:
+    """The file and every local header it includes, recursively."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for line in f:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                for d in (CSRC, INCLUDE):
+                    h = os.path.join(d, m.group(1))
+                    if os.path.exists(h):
+                        _deps(h, seen)
+                        break
+    return seen
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if all(t >= os.path.getmtime(d) for d in _deps(os.path.join(CSRC, src))):
+            return obj
     cmd = [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -41,12 +65,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental=True, only those older
+    than their object file or any header) and link libpfft.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,5 +85,5 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -11,13 +11,16 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pfft.h"
@@ -129,19 +132,6 @@ struct Layout {
     }
 
     int64_t total() const { return rank_off[P]; }
-
-    // Global multi-index of the element at buffer offset e.
-    void global_index(int64_t e, int64_t *g) const
-    {
-        const int64_t r = (int64_t)(std::upper_bound(rank_off.begin(), rank_off.end(), e) - rank_off.begin()) - 1;
-        int64_t ls[kMaxDims], st[kMaxDims];
-        block(r, ls, st);
-        int64_t t = e - rank_off[r];
-        for (int m = ndim - 1; m >= 0; m--) {
-            g[m] = st[m] + t % ls[m];
-            t /= ls[m];
-        }
-    }
 
     // Local extent of axis m in a block whose coordinate along m's direction is c.
     int64_t local_extent(int m, int64_t c) const
@@ -574,6 +564,7 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     }
     // runs shorter than a tile are chained only for the Stockham stage kernels
     build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig);
+    if (ln.kind == KIND_C2C && !ln.contig && tu.xcd_order != 0) ln.xcd = tu.xcd_order == 1 ? 1 : 0;
     return PFFT_OK;
 }
 
@@ -797,6 +788,7 @@ static pfft_tuning default_tuning()
     t.tile_strided = 5;  // by length: 3 below 1024 points, 4 from 1024 on
     t.resident_contig = 0;
     t.resident_strided = 0;
+    t.xcd_order = 0;
     return t;
 }
 
@@ -965,11 +957,24 @@ static int work_buffers(const pfft_plan_s *p)
 // Run a launch list so that the last launch writes `out` (buffers as
 // assign_buffers chooses); forward_factors selects the norm's forward or
 // backward per-axis factors.
+// Byte ranges [a, a + na) and [b, b + nb) share a byte.
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Bytes of the buffer of layout `lid` (real layouts hold reals).
+static size_t layout_bytes(const pfft_plan_s *p, int lid)
+{
+    return (size_t)p->layouts[lid].total() * (lid == p->real0 ? p->elem / 2 : p->elem);
+}
+
 static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void *in, void *out, void *work,
                     bool forward_factors, int sign, int r2c_flags, hipStream_t stream, int direction)
 {
     if (p->flags & PFFT_LAYOUTS_ONLY) return fail(PFFT_EUNSUPPORTED, "plan was created with PFFT_LAYOUTS_ONLY");
-    if (!p->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     if (!in || !out) return fail(PFFT_EINVAL, "null buffer");
     // full aligned tiles move 16-byte pieces at offsets the plan checked
     // relative to the buffers' starts
@@ -978,7 +983,19 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
     const int n = (int)list.size();
     std::vector<const void *> srcs;
     std::vector<void *> dsts;
-    if (assign_buffers(p, list, in, out, work, srcs, dsts) > 0 && !work) return fail(PFFT_EINVAL, "null workspace");
+    const int used = assign_buffers(p, list, in, out, work, srcs, dsts);
+    if (used > 0 && !work) return fail(PFFT_EINVAL, "null workspace");
+    if (n > 0) {
+        // a stage that read and wrote overlapping buffers would race
+        const bool destroy = (p->flags & PFFT_DESTROY_INPUT) != 0 && list[0].src != p->real0;
+        const size_t in_b = destroy ? std::max(layout_bytes(p, list[0].src), p->spec_bytes)
+                                    : layout_bytes(p, list[0].src);
+        const size_t out_b = layout_bytes(p, list.back().dst);
+        const size_t work_b = (size_t)used * ((p->spec_bytes + 255) & ~(size_t)255);
+        if (overlap(in, in_b, out, out_b) || overlap(in, in_b, work, work_b) || overlap(out, out_b, work, work_b))
+            return fail(PFFT_EINVAL, "in, out and work must not overlap");
+    }
+    if (!p->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     for (int k = 0; k < n; k++) {
         const Launch &ln = list[k];
         double scale = (ln.kind == KIND_COPY) ? 1.0 : axis_scale(p, ln.scale_axis, forward_factors);
@@ -991,15 +1008,18 @@ static int run_list(pfft_plan_s *p, const std::vector<Launch> &list, const void 
 
 // Host emulation of the address arithmetic every kernel of a launch performs:
 // all reads and writes must stay inside their buffers and every destination
-// element must be written exactly once.
+// element must be written exactly once.  Tiles are checked in parallel (host
+// threads over ranges of tiles; write counts are atomic).
 static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *what)
 {
     const Layout &A = p->layouts[ln.src];
     const Layout &B = p->layouts[ln.dst];
     const Layout *S[2] = {&A, &B};
+    const int nd = A.ndim;
     const int64_t size[2] = {A.total(), B.total()};
     // positions per side along the axis (real side of R2C/C2R is N real values)
-    int64_t npos[2] = {A.shape[ln.axis], B.shape[ln.axis]};
+    const int64_t npos[2] = {A.shape[ln.axis], B.shape[ln.axis]};
+    const int64_t jall = std::max(npos[0], npos[1]);
     // the element read and the element written at one position are the same
     // global element (C2C and COPY: every axis; R2C/C2R: every other axis)
     const bool same_pos = npos[0] == npos[1];
@@ -1008,85 +1028,124 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
     if (ln.ntiles >= ((int64_t)1 << 31)) return fail(PFFT_EINTERNAL, std::string(what) + ": grid too large");
     const int32_t *pos[2], *na[2];
     const int64_t *roff[2];
+    // every rank's block shape and global start, per side
+    std::vector<int64_t> bls[2], bst[2];
     for (int s = 0; s < 2; s++) {
         pos[s] = (const int32_t *)(p->blob.data() + ln.off_pos[s]);
         na[s] = (const int32_t *)(p->blob.data() + ln.off_na[s]);
         roff[s] = (const int64_t *)(p->blob.data() + ln.off_rank[s]);
+        const Layout &L = *S[s];
+        bls[s].resize((size_t)L.P * nd);
+        bst[s].resize((size_t)L.P * nd);
+        for (int64_t r = 0; r < L.P; r++) L.block(r, &bls[s][(size_t)r * nd], &bst[s][(size_t)r * nd]);
     }
-    std::vector<int64_t> ad;  // the tile's addresses, (line, position, side)
-    for (int64_t ti = 0; ti < ln.ntiles; ti++) {
-        const Tile &t = tiles[ti];
-        if (t.count < 1 || t.count > ln.cfg.W) return fail(PFFT_EINTERNAL, std::string(what) + ": tile count");
-        const int64_t jall = std::max(npos[0], npos[1]);
-        ad.assign((size_t)t.count * (size_t)jall * 2, -1);
-        if (t.run < 0 || (t.run > 0 && (ln.contig || t.b0 < 0 || t.b0 >= t.run)))
-            return fail(PFFT_EINTERNAL, std::string(what) + ": tile run");
-        for (int w = 0; w < t.count; w++) {
-            const int64_t jmax = std::max(npos[0], npos[1]);
-            for (int64_t j = 0; j < jmax; j++) {
-                int64_t addr[2] = {-1, -1};
-                for (int s = 0; s < 2; s++) {
-                    if (j >= npos[s]) continue;
-                    const Layout &L = *S[s];
-                    int c = pos[s][2 * j], loc = pos[s][2 * j + 1];
-                    int64_t rank = t.rank[s] + (int64_t)c * ln.R[s];
-                    if (rank < 0 || rank >= L.P) return fail(PFFT_EINTERNAL, std::string(what) + ": rank");
-                    int64_t O = t.O[s], I = t.I[s];
-                    if (t.run > 0) {
-                        const int64_t q = t.b0 + w;
-                        O += q / t.run;
-                        I += q % t.run;
-                        // the kernels step between runs by ostr elements
-                        const int64_t a0 = roff[s][rank] + ((int64_t)t.O[s] * na[s][c] + loc) * t.E[s] + t.I[s];
-                        const int64_t a1 = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
-                        if (a1 - a0 != (q % t.run) + (q / t.run) * (int64_t)t.ostr[s])
-                            return fail(PFFT_EINTERNAL, std::string(what) + ": run stride");
-                    } else if (ln.contig) {
-                        O += w;
-                    } else {
-                        I += w;
+    std::atomic<bool> failed{false};
+    std::mutex mu;
+    std::string first_error;
+    auto report = [&](const std::string &msg) {
+        std::lock_guard<std::mutex> g(mu);
+        if (!failed.exchange(true)) first_error = msg;
+    };
+    auto check_tiles = [&](int64_t t_begin, int64_t t_end) {
+        std::vector<int64_t> ad;  // the tile's addresses, (line, position, side)
+        for (int64_t ti = t_begin; ti < t_end && !failed.load(std::memory_order_relaxed); ti++) {
+            const Tile &t = tiles[ti];
+            if (t.count < 1 || t.count > ln.cfg.W) return report(std::string(what) + ": tile count");
+            ad.assign((size_t)t.count * (size_t)jall * 2, -1);
+            if (t.run < 0 || (t.run > 0 && (ln.contig || t.b0 < 0 || t.b0 >= t.run)))
+                return report(std::string(what) + ": tile run");
+            for (int w = 0; w < t.count; w++) {
+                for (int64_t j = 0; j < jall; j++) {
+                    int64_t addr[2] = {-1, -1}, rank_of[2] = {0, 0};
+                    for (int s = 0; s < 2; s++) {
+                        if (j >= npos[s]) continue;
+                        const Layout &L = *S[s];
+                        int c = pos[s][2 * j], loc = pos[s][2 * j + 1];
+                        int64_t rank = t.rank[s] + (int64_t)c * ln.R[s];
+                        if (rank < 0 || rank >= L.P) return report(std::string(what) + ": rank");
+                        int64_t O = t.O[s], I = t.I[s];
+                        if (t.run > 0) {
+                            const int64_t q = t.b0 + w;
+                            O += q / t.run;
+                            I += q % t.run;
+                            // the kernels step between runs by ostr elements
+                            const int64_t a0 = roff[s][rank] + ((int64_t)t.O[s] * na[s][c] + loc) * t.E[s] + t.I[s];
+                            const int64_t a1 = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
+                            if (a1 - a0 != (q % t.run) + (q / t.run) * (int64_t)t.ostr[s])
+                                return report(std::string(what) + ": run stride");
+                        } else if (ln.contig) {
+                            O += w;
+                        } else {
+                            I += w;
+                        }
+                        addr[s] = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
+                        rank_of[s] = rank;
+                        ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s] = addr[s];
+                        if (I < 0 || I >= t.E[s] || addr[s] < roff[s][rank] || addr[s] >= roff[s][rank + 1] ||
+                            addr[s] >= size[s])
+                            return report(std::string(what) + ": address out of its block");
+                        if (s == 1 && __atomic_fetch_add(&hits[(size_t)addr[s]], (uint8_t)1, __ATOMIC_RELAXED) == 255)
+                            return report(std::string(what) + ": overflow");
                     }
-                    addr[s] = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
-                    ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s] = addr[s];
-                    if (I < 0 || I >= t.E[s] || addr[s] < roff[s][rank] || addr[s] >= roff[s][rank + 1] ||
-                        addr[s] >= size[s])
-                        return fail(PFFT_EINTERNAL, std::string(what) + ": address out of its block");
-                    if (s == 1) {
-                        if (hits[addr[s]] == 255) return fail(PFFT_EINTERNAL, std::string(what) + ": overflow");
-                        hits[addr[s]]++;
+                    if (j < npos[0] && j < npos[1]) {
+                        // global index of both elements, from their rank block and offset in it
+                        int64_t g[2][kMaxDims];
+                        for (int s = 0; s < 2; s++) {
+                            const int64_t *ls = &bls[s][(size_t)rank_of[s] * nd];
+                            const int64_t *st = &bst[s][(size_t)rank_of[s] * nd];
+                            int64_t e = addr[s] - roff[s][rank_of[s]];
+                            for (int m = nd - 1; m >= 0; m--) {
+                                g[s][m] = st[m] + e % ls[m];
+                                e /= ls[m];
+                            }
+                        }
+                        for (int m = 0; m < nd; m++)
+                            if ((m != ln.axis || same_pos) && g[0][m] != g[1][m])
+                                return report(std::string(what) + ": source and destination differ");
+                        if (g[0][ln.axis] != j && same_pos) return report(std::string(what) + ": position");
                     }
-                }
-                if (j < npos[0] && j < npos[1]) {
-                    int64_t g0[kMaxDims], g1[kMaxDims];
-                    A.global_index(addr[0], g0);
-                    B.global_index(addr[1], g1);
-                    for (int m = 0; m < A.ndim; m++)
-                        if ((m != ln.axis || same_pos) && g0[m] != g1[m])
-                            return fail(PFFT_EINTERNAL, std::string(what) + ": source and destination differ");
-                    if (g0[ln.axis] != j && same_pos)
-                        return fail(PFFT_EINTERNAL, std::string(what) + ": position");
                 }
             }
-        }
-        // the alignment flags promise groups of G adjacent elements starting
-        // at a multiple of G: lines 2i.. (strided) or positions 2i.. of every
-        // line (contiguous), G = 2 (bit 0) or 4 (bit 1), on both sides
-        for (int bit = 0; bit < 2; bit++) {
-            if (!(t.flags & (1 << bit))) continue;
-            const int64_t G = bit == 0 ? 2 : 4;
-            for (int s = 0; s < 2; s++)
-                for (int w = 0; w < t.count; w++)
-                    for (int64_t j = 0; j < npos[s]; j++) {
-                        const bool first = ln.contig ? (j % G == 0) : (w % G == 0 && w + G <= t.count);
-                        if (!first) continue;
-                        const int64_t a0 = ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s];
-                        bool ok = a0 % G == 0 && (!ln.contig || j + G <= npos[s]);
-                        for (int64_t k = 1; k < G && ok; k++) {
-                            const int64_t wk = ln.contig ? w : w + k, jk = ln.contig ? j + k : j;
-                            ok = ad[((size_t)wk * (size_t)jall + (size_t)jk) * 2 + (size_t)s] == a0 + k;
+            // the alignment flags promise groups of G adjacent elements starting
+            // at a multiple of G: lines 2i.. (strided) or positions 2i.. of every
+            // line (contiguous), G = 2 (bit 0) or 4 (bit 1), on both sides
+            for (int bit = 0; bit < 2; bit++) {
+                if (!(t.flags & (1 << bit))) continue;
+                const int64_t G = bit == 0 ? 2 : 4;
+                for (int s = 0; s < 2; s++)
+                    for (int w = 0; w < t.count; w++)
+                        for (int64_t j = 0; j < npos[s]; j++) {
+                            const bool first = ln.contig ? (j % G == 0) : (w % G == 0 && w + G <= t.count);
+                            if (!first) continue;
+                            const int64_t a0 = ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s];
+                            bool ok = a0 % G == 0 && (!ln.contig || j + G <= npos[s]);
+                            for (int64_t k = 1; k < G && ok; k++) {
+                                const int64_t wk = ln.contig ? w : w + k, jk = ln.contig ? j + k : j;
+                                ok = ad[((size_t)wk * (size_t)jall + (size_t)jk) * 2 + (size_t)s] == a0 + k;
+                            }
+                            if (!ok) return report(std::string(what) + ": tile alignment flag");
                         }
-                        if (!ok) return fail(PFFT_EINTERNAL, std::string(what) + ": tile alignment flag");
-                    }
+            }
+        }
+    };
+    const int64_t work = ln.ntiles * std::max<int64_t>(1, jall) * 64;  // rough cost per tile
+    int nthreads = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (work < ((int64_t)1 << 22)) nthreads = 1;
+    if (nthreads > ln.ntiles) nthreads = (int)std::max<int64_t>(1, ln.ntiles);
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nthreads; k++)
+        pool.emplace_back(check_tiles, ln.ntiles * k / nthreads, ln.ntiles * (k + 1) / nthreads);
+    check_tiles(0, ln.ntiles / nthreads);
+    for (auto &th : pool) th.join();
+    if (failed.load()) return fail(PFFT_EINTERNAL, first_error);
+    if (ln.xcd) {
+        // the kernel's XCD tile order (one tile per workgroup) must visit every tile once
+        std::vector<uint8_t> seen((size_t)ln.ntiles, 0);
+        const int64_t nt = ln.ntiles, q = nt / 8, r = nt % 8;
+        for (int64_t b = 0; b < nt; b++) {
+            const int64_t x = b % 8, k = b / 8, ti = x * q + std::min(x, r) + k;
+            if (ti < 0 || ti >= nt || seen[(size_t)ti]++)
+                return fail(PFFT_EINTERNAL, std::string(what) + ": XCD tile order is not a permutation");
         }
     }
     for (int64_t e = 0; e < size[1]; e++)
@@ -1348,7 +1407,8 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
     PFFT_GUARD_BEGIN
     if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
     if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 5 ||
-        t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1)
+        t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1 ||
+        t->xcd_order < 0 || t->xcd_order > 2)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again
     plan->tuning = *t;
@@ -1496,10 +1556,12 @@ int pfft_redistribute(pfft_plan plan, int layout_from, int layout_to, const void
 {
     PFFT_GUARD_BEGIN
     if (!plan || !in || !out) return fail(PFFT_EINVAL, "null argument");
-    if (!plan->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     int n = plan->nlayouts;
     if (layout_from < 0 || layout_from >= n || layout_to < 0 || layout_to >= n)
         return fail(PFFT_EINVAL, "layout out of range");
+    if (overlap(in, layout_bytes(plan, layout_from), out, layout_bytes(plan, layout_to)))
+        return fail(PFFT_EINVAL, "in and out must not overlap");
+    if (!plan->dev) return fail(PFFT_EWORKSPACE, "device state not bound");
     if (layout_to == layout_from + 1) return run_launch(plan, plan->up[layout_from], in, out, 1.0, -1, 0, stream);
     if (layout_to == layout_from - 1) return run_launch(plan, plan->down[layout_to], in, out, 1.0, -1, 0, stream);
     return fail(PFFT_EINVAL, "layouts must be chain neighbours (one exchange apart)");
@@ -1678,6 +1740,9 @@ int pfft_batch_bind(pfft_batch b, void *state, void *in, void *out, void *work, 
     if (((uintptr_t)state & 255u) != 0) return fail(PFFT_EINVAL, "device state must be 256-byte aligned");
     if (((uintptr_t)in | (uintptr_t)out | (uintptr_t)work) & 15u)
         return fail(PFFT_EINVAL, "in, out and work must be 16-byte aligned");
+    if (overlap(in, b->in_bytes, out, b->out_bytes) || overlap(in, b->in_bytes, work, b->work_bytes) ||
+        overlap(out, b->out_bytes, work, b->work_bytes))
+        return fail(PFFT_EINVAL, "in, out and work must not overlap");
     b->dev = state;
     b->in = in;
     b->out = out;

@@ -90,11 +90,31 @@ def test_calls_before_binding_fail_cleanly():
     lib = _lib.load()
     from paper_1804_09536_amd.plan import Plan
     p = Plan((16, 16, 16), (2, 2))
-    st = lib.pfft_forward(p._h, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), None)
-    assert st == -6
+    v = ctypes.c_void_p
+    a, b, c = v(1 << 20), v(1 << 24), v(1 << 28)   # stand-in addresses, never dereferenced
+    assert lib.pfft_forward(p._h, a, b, c, None) == -6
     assert lib.pfft_forward(None, None, None, None, None) == -1
-    assert lib.pfft_redistribute(p._h, 0, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -6
+    assert lib.pfft_redistribute(p._h, 0, 2, a, b, None) == -6
     assert _lib.strerror(-5) == "unsupported transform length"
+
+
+def test_overlapping_buffers_are_refused():
+    # checked before anything touches the device: a stage reading and writing
+    # overlapping buffers would race
+    lib = _lib.load()
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan((16, 16, 16), (2, 2))   # 16^3 complex64: 32 KiB per buffer
+    nb = 16 ** 3 * 8
+    v = ctypes.c_void_p
+    base = 1 << 24
+    far = v(base + 4 * nb)
+    for fn in (lib.pfft_forward, lib.pfft_backward, lib.pfft_adjoint_forward, lib.pfft_adjoint_backward):
+        assert fn(p._h, v(base), v(base), far, None) == -1                  # in == out
+        assert fn(p._h, v(base), v(base + nb - 16), far, None) == -1        # out starts inside in
+        assert fn(p._h, v(base), v(base + nb), v(base + nb + 4096), None) == -1   # work inside out
+        assert fn(p._h, v(base), v(base + nb), far, None) == -6             # disjoint: not bound yet
+    assert lib.pfft_redistribute(p._h, 0, 1, v(base), v(base + 256), None) == -1
+    assert lib.pfft_redistribute(p._h, 0, 1, v(base), v(base + nb), None) == -6
 
 
 @pytest.mark.parametrize("shape,grid,kind,placement,path,plain,destroyed", [

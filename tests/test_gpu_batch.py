@@ -90,3 +90,64 @@ def test_batch_graph_replay():
         for m in range(len(plans)):
             b.inputs[m].copy_(torch.from_numpy(data[m]))
         torch.cuda.synchronize()
+
+
+# The mixed batch of the batching workload: one instance of each shape, three
+# field components each (seeds [6, shape, instance, component]), on the grids
+# the bench uses; 384^3 and 128x256x512 run the radix-3 and the 512-point
+# strided kernels inside the multi-transform launches.
+CONFIG5 = [((64, 64, 64), (4,)), ((96, 96, 96), (8,)), ((128, 128, 128), (4, 4)), ((192, 192, 192), (4, 4)),
+           ((256, 256, 256), (4, 4)), ((384, 384, 384), (8, 8)), ((128, 256, 512), (4, 8))]
+
+
+@pytest.fixture(scope="module")
+def config5_batch():
+    plans = [Plan(s, g) for s, g in CONFIG5]
+    members = [p for p in plans for _ in range(3)]
+    print("config5 batch of", len(members), "members", flush=True)
+    b = Batch(members)
+    data = []
+    for m, x in enumerate(b.inputs):
+        u = inputs.uniform_complex(x.numel(), [6, m // 3, 0, m % 3], np.complex64)
+        x.copy_(torch.from_numpy(u))
+        data.append(u)
+    b.forward()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in b.outputs]
+    outs = [o.cpu().numpy() for o in b.outputs]
+    # the same batch captured in a graph replays to the same bits
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            b.forward()
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for o in b.outputs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        replay_equal = all(torch.equal(b.outputs[m], eager[m]) for m in range(len(members)))
+        assert replay_equal, rep
+    del eager
+    b.backward()
+    torch.cuda.synchronize()
+    backs = [i.cpu().numpy() for i in b.inputs]
+    print("config5 batch done", flush=True)
+    return members, data, outs, backs
+
+
+@pytest.mark.parametrize("sid", range(len(CONFIG5)), ids=["x".join(map(str, s)) for s, _ in CONFIG5])
+def test_config5_batch_matches_oracle(config5_batch, sid):
+    members, data, outs, backs = config5_batch
+    shape, grid = CONFIG5[sid]
+    ch = oracle.Chain.paper(shape, grid)
+    for c in range(3):
+        m = 3 * sid + c
+        expect = oracle.forward(ch, data[m].astype(np.complex128))
+        assert np.linalg.norm(outs[m] - expect) / np.linalg.norm(expect) <= 1e-5, (shape, c)
+        expect_b = oracle.backward(ch, outs[m].astype(np.complex128))
+        assert np.linalg.norm(backs[m] - expect_b) / np.linalg.norm(expect_b) <= 1e-5, (shape, c)

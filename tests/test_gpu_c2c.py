@@ -93,6 +93,54 @@ def test_c2c_matches_oracle(shape, grid, chain, prec):
     assert _host(x).tobytes() == u.tobytes()
 
 
+# Shapes whose strided 512-point stage runs the dominant kernel of the metric
+# workload (default strided tiles: 32 complex64 / 16 complex128 lines in two
+# LDS portions), once by the plan's rule (round-robin tiles at these sizes)
+# and once with the XCD tile order forced on, as at full size.
+STRIDED512 = [((512, 16, 32), (2, 2)), ((16, 512, 64), (4, 2)), ((512, 8, 64), (2, 4))]
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape,grid", STRIDED512)
+def test_c2c_strided512_dominant_kernel(shape, grid, prec, xcd):
+    print("case", shape, grid, prec, xcd, flush=True)
+    p = Plan(shape, grid, precision=prec)
+    p.set_tuning(xcd_order=xcd)
+    p.validate()
+    ch = oracle.Chain.paper(shape, grid)
+    n = p.buffer_numel(0)
+    u = inputs.uniform_complex(n, [21, n], NPDT[prec])
+    y = p.forward(_to_dev(u))
+    got = _host(y)
+    assert relerr(got, oracle.forward(ch, u.astype(np.complex128))) <= TOL[prec]
+    z = _host(p.backward(y))
+    assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= TOL[prec]
+
+
+# The lengths of the mixed batch (3 * 2^a) and the other long radix lengths,
+# along a strided axis (axis 0, split in the input layout) and along the
+# contiguous last axis.
+LONG = [192, 384, 768, 1536, 2048, 3072, 4096]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["strided", "contig"])
+@pytest.mark.parametrize("N", LONG)
+def test_c2c_long_lengths(N, mode, prec):
+    shape, grid = ((N, 8, 16), (4, 2)) if mode == "strided" else ((8, 16, N), (2, 2))
+    print("case", shape, grid, prec, flush=True)
+    p = Plan(shape, grid, precision=prec)
+    ch = oracle.Chain.paper(shape, grid)
+    n = p.buffer_numel(0)
+    u = inputs.uniform_complex(n, [22, N], NPDT[prec])
+    y = p.forward(_to_dev(u))
+    got = _host(y)
+    assert relerr(got, oracle.forward(ch, u.astype(np.complex128))) <= TOL[prec]
+    z = _host(p.backward(y))
+    assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= TOL[prec]
+
+
 @pytest.mark.parametrize("norm", ["backward", "none"])
 def test_c2c_other_norms(norm):
     shape, grid = (32, 16, 64), (2, 4)
@@ -146,15 +194,19 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
     names = ("gather", "scatter", "direct", "final")
     for placement in itertools.product(names, names):
         p = Plan(shape, grid, kind=kind, placement=placement)
-        # every tile knob with one placement per chain; the default knobs with the mixed pairs
-        knobs = (itertools.product((0, 1, 2, 3, 4), (0, 1, 2, 3, 4), (0, 1), (0, 1))
-                 if placement[0] == placement[1] else [tuple(p.tuning().values())])
-        for tc, ts, rc, rs in knobs:
-            p.set_tuning(tile_contig=tc, tile_strided=ts, resident_contig=rc, resident_strided=rs)
+        d = p.tuning()
+        default = (d["tile_contig"], d["tile_strided"], d["resident_contig"], d["resident_strided"], 0)
+        # every tile knob with one placement per chain; the default knobs with the mixed pairs;
+        # the XCD tile order forced on and off with the default tiles
+        knobs = (list(itertools.product((0, 1, 2, 3, 4), (0, 1, 2, 3, 4), (0, 1), (0, 1), (0,)))
+                 if placement[0] == placement[1] else [default])
+        knobs += [default[:4] + (1,), default[:4] + (2,)]
+        for tc, ts, rc, rs, xo in knobs:
+            p.set_tuning(tile_contig=tc, tile_strided=ts, resident_contig=rc, resident_strided=rs, xcd_order=xo)
             got = _host(p.forward(x))
-            assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs)
+            assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs, xo)
             back = _host(p.backward(_to_dev(ref)))
-            assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs)
+            assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs, xo)
 
 
 @pytest.mark.parametrize("shape,grid,kind,placement,path", [

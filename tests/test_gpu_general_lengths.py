@@ -53,8 +53,11 @@ def test_general_length_real_and_complex(shape, grid, prec):
             x64 = x.astype(np.float64)
         y = p.forward(torch.from_numpy(x).cuda())
         got = _host(y)
-        assert np.linalg.norm(got - oracle.forward(ch, x64)) / np.linalg.norm(got) <= tol
+        e = oracle.forward(ch, x64)
+        assert np.linalg.norm(got - e) / np.linalg.norm(e) <= tol
         back = _host(p.backward(y))
-        assert np.linalg.norm(back - oracle.backward(ch, got.astype(np.complex128))) / np.linalg.norm(back) <= tol
+        e = oracle.backward(ch, got.astype(np.complex128))
+        assert np.linalg.norm(back - e) / np.linalg.norm(e) <= tol
         adj = _host(p.adjoint_forward(y))
-        assert np.linalg.norm(adj - oracle.adjoint_forward(ch, got.astype(np.complex128))) / np.linalg.norm(adj) <= tol
+        e = oracle.adjoint_forward(ch, got.astype(np.complex128))
+        assert np.linalg.norm(adj - e) / np.linalg.norm(e) <= tol

@@ -97,8 +97,34 @@ def test_loss_gradient_exact_central_differences():
 
 
 def test_wavenumber_weight_values():
-    w = oracle.wavenumber_weight((4, 6, 4), real_last=True)
+    w = oracle.wavenumber_weight((4, 6, 4), real_last=True, hermitian=False)
     assert w.shape == (4, 6, 4)
     # axis 0 wavenumbers 0,1,-2,-1; axis 1 0,1,2,-3,-2,-1; half axis 0..3
     assert w[2, 3, 3] == 4 + 9 + 9
     assert w[3, 5, 1] == 1 + 1 + 1
+    # Hermitian weight of the half axis of a real length 6: bins 1 and 2 stand
+    # for two bins each, bins 0 and 3 (the Nyquist bin) for one
+    wh = oracle.wavenumber_weight((4, 6, 4), real_last=True)
+    assert wh[2, 3, 3] == 4 + 9 + 9
+    assert wh[3, 5, 1] == 2 * (1 + 1 + 1)
+    assert wh[1, 1, 0] == 1 + 1
+    # an odd real length 7 has no Nyquist bin: bins 1..3 all double
+    wo = oracle.wavenumber_weight((2, 2, 4), real_last=True, real_n=7)
+    assert wo[0, 0, 3] == 2 * 9
+
+
+@pytest.mark.parametrize("shape,grid", [((8, 6, 10), (2, 3)), ((6, 4, 7), (2,)), ((4, 6, 4, 6), (2, 1, 3))])
+def test_hermitian_loss_equals_full_spectrum_sum(shape, grid):
+    # the half-spectrum loss with the Hermitian weight equals sum over ALL k
+    # of |k|^2 |FFT(u)(k)|^2, computed from the full complex transform of the
+    # same real field (numpy's fftn, a library special case of Eq. multifft)
+    ch = oracle.Chain.paper(shape, grid, kind="r2c")
+    n = int(np.prod(shape))
+    u = inputs.gaussian_real(n, [25], np.float64)
+    wg = oracle.wavenumber_weight(ch.spectral_shape(), real_last=True, real_n=shape[-1])
+    w = np.real(oracle.scatter_global(wg.astype(np.complex128), ch.output_layout()))
+    loss, _ = oracle.loss_and_grad(ch, u, w)
+    G = oracle.gather_global(u, ch.layout(0, spectral=False))
+    full = np.fft.fftn(G, norm="forward")
+    wf = oracle.wavenumber_weight(shape, real_last=False)
+    assert abs(loss - float(np.sum(wf * np.abs(full) ** 2))) <= 1e-12 * abs(loss)
