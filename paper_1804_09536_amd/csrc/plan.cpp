@@ -912,26 +912,31 @@ static int assign_buffers(const pfft_plan_s *p, const std::vector<Launch> &list,
     int used = 0;
     srcs.assign(n, nullptr);
     dsts.assign(n, nullptr);
+    // (the workspace buffers in use are counted where they are chosen: the
+    // caller's pointers may coincide with w1's address)
     for (int k = 0; k < n; k++) {
         void *dst;
+        int slot = -1;  // workspace buffer taken by this launch
         if (k == n - 1) {
             dst = out;
         } else if (out_is_real) {
             if (destroy)
-                dst = (k % 2 == 0) ? (void *)w0 : in_w;
+                slot = (k % 2 == 0) ? 0 : -1;
             else
-                dst = (k % 2 == 0) ? (void *)w0 : (void *)w1;
+                slot = k % 2;
+            dst = slot == 0 ? (void *)w0 : slot == 1 ? (void *)w1 : in_w;
         } else if ((n - 1 - k) % 2 == 0) {
             dst = out;
         } else if (destroy) {
             // only the first launch can land on `in`; in place if it keeps its layout
             const bool in_place = list[0].src == list[0].dst && list[0].kind == KIND_C2C;
-            dst = (k > 0 || in_place) ? in_w : (void *)w0;
+            slot = (k > 0 || in_place) ? -1 : 0;
+            dst = slot == 0 ? (void *)w0 : in_w;
         } else {
+            slot = 0;
             dst = w0;
         }
-        if (dst == (void *)w0) used = std::max(used, 1);
-        if (dst == (void *)w1) used = 2;
+        used = std::max(used, slot + 1);
         srcs[k] = cur;
         dsts[k] = dst;
         cur = dst;

@@ -113,6 +113,9 @@ def test_overlapping_buffers_are_refused():
         assert fn(p._h, v(base), v(base + nb - 16), far, None) == -1        # out starts inside in
         assert fn(p._h, v(base), v(base + nb), v(base + nb + 4096), None) == -1   # work inside out
         assert fn(p._h, v(base), v(base + nb), far, None) == -6             # disjoint: not bound yet
+        # disjoint, with `out` right after the workspace (where a second workspace
+        # buffer would start): still disjoint
+        assert fn(p._h, v(base), v(base + 2 * nb), v(base + nb), None) == -6
     assert lib.pfft_redistribute(p._h, 0, 1, v(base), v(base + 256), None) == -1
     assert lib.pfft_redistribute(p._h, 0, 1, v(base), v(base + nb), None) == -6
 
