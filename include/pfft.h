@@ -338,6 +338,23 @@ int pfft_weighted_energy(int precision, int64_t n, const void *u, const void *w,
                          hipStream_t stream);
 
 /*
+ * pfft_weighted_energy for callers that cannot allocate device memory or
+ * provide scratch (code under HIP graph capture, tight training or serving
+ * loops): the same kernels and result, with the partial sums in the library's
+ * own static device scratch of PFFT_ENERGY_PARTIALS doubles (8 KiB per
+ * device, held until the process ends; every n fits it: the kernels use at
+ * most that many partial sums).  Allocates nothing and calls no allocating
+ * routine; the scratch's device address is looked up once per device on its
+ * first call (with the current device set to the device of `stream` and the
+ * buffers).  All calls on one device share the scratch: calls that overlap
+ * in time on one device (e.g. on two streams) race and give wrong losses;
+ * calls ordered on one stream are safe.  Arguments and errors as
+ * pfft_weighted_energy (PFFT_EHIP if the scratch cannot be looked up).
+ */
+int pfft_weighted_energy_noalloc(int precision, int64_t n, const void *u, const void *w, void *loss,
+                                 hipStream_t stream);
+
+/*
  * Its gradient under torch's convention for complex inputs:
  *   grad_i = 2 g w_i u_i,  g = *g_dev (one real of the precision, on the
  * device: the incoming gradient of the loss).  grad may not overlap u.

@@ -87,6 +87,7 @@ def load():
         "pfft_adjoint_backward": [vp, vp, vp, vp, vp],
         "pfft_weighted_energy": [c_int, ctypes.c_int64, vp, vp, vp, vp, vp],
         "pfft_weighted_energy_grad": [c_int, ctypes.c_int64, vp, vp, vp, vp, vp],
+        "pfft_weighted_energy_noalloc": [c_int, ctypes.c_int64, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)

@@ -7,10 +7,17 @@
 // not depend on scheduling.  HBM-bound: one read of u and w per pass.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fft_device.hpp"
 #include "pfft_kernels.hpp"
 
 namespace pfft {
+
+// Scratch of the allocation-free entry point: room for the FP64 partial sums
+// of one energy call (kEnergyPartials doubles, 8 KiB).  Each device holds its
+// own copy for the life of the process; every call on a device shares it.
+static __device__ __align__(256) double scratch[kEnergyPartials];
 
 constexpr int kEnergyThreads = 256;
 
@@ -90,6 +97,40 @@ hipError_t energy_launch(int prec, long n, const void *u, const void *w, double 
                            (double *)loss);
     }
     return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept: in host code the array's name
+// is only a host-side stand-in, never a device address.
+static hipError_t scratch_address(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (double *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t energy_launch_noalloc(int prec, long n, const void *u, const void *w, void *loss, hipStream_t s)
+{
+    // every partial the total reads is written by this call's first kernel
+    // (earlier calls' contents are never read), so nothing is cleared
+    if (energy_blocks(n) > kEnergyPartials) return hipErrorInvalidValue;
+    double *partials = nullptr;
+    hipError_t e = scratch_address(&partials);
+    if (e != hipSuccess) return e;
+    return energy_launch(prec, n, u, w, partials, loss, s);
 }
 
 hipError_t energy_grad_launch(int prec, long n, const void *u, const void *w, const void *g, void *grad, hipStream_t s)

@@ -61,5 +61,8 @@ constexpr int kEnergyPartials = 1024;
 hipError_t energy_launch(int prec, long n, const void *u, const void *w, double *partials, void *loss, hipStream_t s);
 hipError_t energy_grad_launch(int prec, long n, const void *u, const void *w, const void *g, void *grad,
                               hipStream_t s);
+// The energy with its partial sums in the library's static per-device scratch
+// (no caller scratch, no allocation).
+hipError_t energy_launch_noalloc(int prec, long n, const void *u, const void *w, void *loss, hipStream_t s);
 
 }  // namespace pfft

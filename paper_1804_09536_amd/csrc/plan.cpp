@@ -1717,6 +1717,20 @@ int pfft_weighted_energy(int precision, int64_t n, const void *u, const void *w,
     PFFT_GUARD_END
 }
 
+int pfft_weighted_energy_noalloc(int precision, int64_t n, const void *u, const void *w, void *loss,
+                                 hipStream_t stream)
+{
+    PFFT_GUARD_BEGIN
+    const size_t r = precision == PFFT_F64 ? 8 : 4;
+    // (the loss pointer stands in for the absent partials in the null check)
+    int rc = energy_args(precision, n, u, w, loss, loss, r, r, true);
+    if (rc) return rc;
+    hipError_t e = energy_launch_noalloc(precision == PFFT_F64 ? 1 : 0, (long)n, u, w, loss, stream);
+    if (e != hipSuccess) return fail(PFFT_EHIP, std::string("energy launch (static scratch): ") + hipGetErrorString(e));
+    return PFFT_OK;
+    PFFT_GUARD_END
+}
+
 int pfft_weighted_energy_grad(int precision, int64_t n, const void *u, const void *w, const void *g_dev, void *grad,
                               hipStream_t stream)
 {
