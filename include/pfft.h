@@ -187,6 +187,12 @@ typedef struct {
                        tiles, lines up to 512 points, destinations beyond 256 MiB), 1 always, 2 never.
                        With it, each of the 8 XCDs (workgroup b runs on XCD b mod 8) takes one
                        contiguous range of tiles. */
+    int stream_strided; /* complex strided stages, full tiles: 0 ordinary loads and stores, 1 streaming
+                           (non-temporal) loads, 2 streaming stores, 3 both, 4 by the plan's rule
+                           (the default): where source and destination together exceed 256 MiB
+                           (the last-level cache), streaming loads, and streaming stores except on
+                           stages with the XCD tile order, whose half-row writes are completed in
+                           L2 by the neighbouring tile; otherwise 0 */
 } pfft_tuning;
 
 int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);

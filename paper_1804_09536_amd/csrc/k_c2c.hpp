@@ -54,7 +54,9 @@ struct C2CDefault {
     using type = C2CCfg<T, N, CONTIG, W, NL>;
 };
 
-template <typename T, int N, bool CONTIG, int SIGN, class S>
+// STREAM: strided tiles may use streaming loads / stores (SF_LOAD_NT,
+// SF_STORE_NT); without it those paths are not generated.
+template <typename T, int N, bool CONTIG, int SIGN, class S, bool STREAM = true>
 struct C2CWorker {
     using T2 = typename V2<T>::type;
     using T4 = typename V2<T>::quad;
@@ -145,18 +147,22 @@ struct C2CWorker {
 #pragma unroll
                 for (int m = 0; m < P; m++) v[l][m] = load_stream(in + src.off[m] + wl[l] * src.stride[m]);
         } else if (fast) {
+            // rows of adjacent lines; streaming loads where the stage asks for them
+            const bool nt = STREAM && (a.flags & SF_LOAD_NT) != 0;
 #pragma unroll
             for (int l = 0; l < NL; l += VEC)
 #pragma unroll
                 for (int m = 0; m < P; m++) {
                     if constexpr (VEC == 2) {
-                        T4 q = *(const T4 *)(in + at(src, lo, wl, l, m));
+                        const T4 *p4 = (const T4 *)(in + at(src, lo, wl, l, m));
+                        T4 q = nt ? load_stream(p4) : *p4;
                         v[l][m].x = q.x;
                         v[l][m].y = q.y;
                         v[l + 1][m].x = q.z;
                         v[l + 1][m].y = q.w;
                     } else {
-                        v[l][m] = in[at(src, lo, wl, l, m)];
+                        const T2 *p2 = in + at(src, lo, wl, l, m);
+                        v[l][m] = nt ? load_stream(p2) : *p2;
                     }
                 }
         } else {
@@ -196,6 +202,7 @@ struct C2CWorker {
 #pragma unroll
                 for (int m = 0; m < P; m++) store_stream(out + dst.off[m] + wl[l] * dst.stride[m], v[l][m]);
         } else if (count > 0) {
+            const bool nt = STREAM && (a.flags & SF_STORE_NT) != 0;
 #pragma unroll
             for (int l = 0; l < NL; l += VEC)
 #pragma unroll
@@ -206,9 +213,17 @@ struct C2CWorker {
                         q.y = v[l][m].y;
                         q.z = v[l + 1][m].x;
                         q.w = v[l + 1][m].y;
-                        *(T4 *)(out + at(dst, lo, wl, l, m)) = q;
+                        T4 *p4 = (T4 *)(out + at(dst, lo, wl, l, m));
+                        if (nt)
+                            store_stream(p4, q);
+                        else
+                            *p4 = q;
                     } else {
-                        out[at(dst, lo, wl, l, m)] = v[l][m];
+                        T2 *p2 = out + at(dst, lo, wl, l, m);
+                        if (nt)
+                            store_stream(p2, v[l][m]);
+                        else
+                            *p2 = v[l][m];
                     }
                 }
         } else {
@@ -295,14 +310,19 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
 
 // The same stage for tiles of several transforms in one launch: each tile
 // carries the index of its transform's arguments in bits 8..31 of its flags.
+// Every transform of one launch has lines of N points in one precision, so
+// they share one twiddle table (e^{-2 pi i m / N}), staged from the first
+// transform's copy.
 template <typename T, int N, bool CONTIG, int SIGN, class S>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c_multi(
     const StageArgs *__restrict__ args, const Tile *__restrict__ tiles, long nt)
 {
-    using Wk = C2CWorker<T, N, CONTIG, SIGN, S>;
+    using Wk = C2CWorker<T, N, CONTIG, SIGN, S, false>;
     using T2 = typename Wk::T2;
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];
+    __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
+    const T2 *tw = TwiddleStage<T2, N>::stage(twl, args[0].twiddle);
     Wk wk;
     wk.init_geometry();
     const long G = gridDim.x;
@@ -314,7 +334,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
         const StageArgs &a = args[(unsigned)t.flags >> 8];
         wk.refresh();
         wk.load(a, t, v, d, c);
-        wk.process(a, t, v, d, c, lds, (const T2 *)a.twiddle);
+        wk.process(a, t, v, d, c, lds, tw);
     }
 }
 

@@ -70,6 +70,8 @@ enum StageFlags : int32_t {
                              // element doubled; type II: special output element halved)
     SF_XCD_ORDER = 32,       // complex strided stage, one tile per workgroup: each of the 8 XCDs
                              // (workgroup b runs on XCD b % 8) takes one contiguous range of tiles
+    SF_LOAD_NT = 64,         // complex strided stage: full aligned tiles read with streaming loads
+    SF_STORE_NT = 128,       // complex strided stage: full aligned tiles written with streaming stores
 };
 
 struct StageArgs {

@@ -195,18 +195,21 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
     for placement in itertools.product(names, names):
         p = Plan(shape, grid, kind=kind, placement=placement)
         d = p.tuning()
-        default = (d["tile_contig"], d["tile_strided"], d["resident_contig"], d["resident_strided"], 0)
+        default = (d["tile_contig"], d["tile_strided"], d["resident_contig"], d["resident_strided"], 0,
+                   d["stream_strided"])
         # every tile knob with one placement per chain; the default knobs with the mixed pairs;
-        # the XCD tile order forced on and off with the default tiles
-        knobs = (list(itertools.product((0, 1, 2, 3, 4), (0, 1, 2, 3, 4), (0, 1), (0, 1), (0,)))
+        # the XCD tile order forced on and off and every streaming mode with the default tiles
+        knobs = (list(itertools.product((0, 1, 2, 3, 4), (0, 1, 2, 3, 4), (0, 1), (0, 1), (0,), (default[5],)))
                  if placement[0] == placement[1] else [default])
-        knobs += [default[:4] + (1,), default[:4] + (2,)]
-        for tc, ts, rc, rs, xo in knobs:
-            p.set_tuning(tile_contig=tc, tile_strided=ts, resident_contig=rc, resident_strided=rs, xcd_order=xo)
+        knobs += [default[:4] + (1, default[5]), default[:4] + (2, default[5])]
+        knobs += [default[:5] + (sm,) for sm in range(5)]
+        for tc, ts, rc, rs, xo, sm in knobs:
+            p.set_tuning(tile_contig=tc, tile_strided=ts, resident_contig=rc, resident_strided=rs, xcd_order=xo,
+                         stream_strided=sm)
             got = _host(p.forward(x))
-            assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs, xo)
+            assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs, xo, sm)
             back = _host(p.backward(_to_dev(ref)))
-            assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs, xo)
+            assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs, xo, sm)
 
 
 @pytest.mark.parametrize("shape,grid,kind,placement,path", [
