@@ -223,31 +223,36 @@ __host__ __device__ constexpr int pow2_part(int N) { return is_pow2(N) ? N : N /
 
 __host__ __device__ constexpr int fft_points_pow2(int N) { return N <= 16 ? N : (N <= 512 ? 8 : 16); }
 
-__host__ __device__ constexpr int fft_points(int N)
+// Points per thread of the power-of-two passes (the largest radix).  For
+// 3 * 2^a lengths the three-fold points per thread would double the
+// registers of the power-of-two plan, so the power-of-two part is halved
+// there: 12 points per thread up to 768 (one more LDS exchange, half the
+// registers: 384^3 -16 %), 24 from 1536 on (whose 16-line tiles measured
+// slower with the extra exchanges).
+__host__ __device__ constexpr int fft_p2(int N)
 {
-    return is_pow2(N) ? fft_points_pow2(N) : 3 * (N == 3 ? 1 : fft_points_pow2(N / 3));
+    if (is_pow2(N)) return fft_points_pow2(N);
+    const int N2 = N / 3;
+    return N2 <= 8 ? N2 : (N2 <= 256 ? 4 : 8);
 }
 
-__host__ __device__ constexpr int fft_npasses_pow2(int N)
+__host__ __device__ constexpr int fft_points(int N) { return is_pow2(N) ? fft_p2(N) : 3 * fft_p2(N); }
+
+__host__ __device__ constexpr int fft_npasses(int N)
 {
-    int P = fft_points_pow2(N), n = 0, rem = N;
+    int n = 0, rem = pow2_part(N);
+    const int P = fft_p2(N);
     while (rem > 1) {
         rem = rem >= P ? rem / P : 1;
         n++;
     }
-    return n;
-}
-
-__host__ __device__ constexpr int fft_npasses(int N)
-{
-    return is_pow2(N) ? fft_npasses_pow2(N) : fft_npasses_pow2(N / 3) + 1;
+    return is_pow2(N) ? n : n + 1;
 }
 
 __host__ __device__ constexpr int fft_radix(int N, int pass)
 {
-    const int N2 = pow2_part(N);
     if (!is_pow2(N) && pass == fft_npasses(N) - 1) return 3;
-    int P = fft_points_pow2(N2), rem = N2;
+    int P = fft_p2(N), rem = pow2_part(N);
     for (int i = 0; i < pass; i++) rem = rem >= P ? rem / P : 1;
     return rem >= P ? P : rem;
 }
