@@ -20,7 +20,7 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
     switch (kind) {
     case KIND_C2C: {
         int rc = prec == 0 ? c2c_config_f32(N, contig, variant, cfg) : c2c_config_f64(N, contig, variant, cfg);
-        return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
+        return rc == 0 ? 0 : mixed_config(prec, N, kind, cfg);
     }
     case KIND_COPY: return copy_config(N, cfg);
     case KIND_R2R:
@@ -29,7 +29,7 @@ int kernel_config(int kind, int prec, int N, int contig, int variant, KernelConf
     case KIND_C2R: {
         if (!contig) return -1;
         int rc = (N % 2 == 0) ? real_config(prec, N, kind, variant, cfg) : -1;
-        return rc == 0 ? 0 : dft_config(prec, N, kind, cfg);
+        return rc == 0 ? 0 : mixed_config(prec, N, kind, cfg);
     }
     default: return -1;
     }
@@ -39,7 +39,7 @@ int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelCo
                  const StageArgs &a, hipStream_t s)
 {
     if (cfg.id < 0 && kind != KIND_COPY && kind != KIND_R2R)
-        return (int)dft_launch(prec, N, kind, contig, sign, cfg, a, s);
+        return (int)mixed_launch(prec, kind, contig, sign, cfg, a, s);
     switch (kind) {
     case KIND_C2C:
         return (int)(prec == 0 ? c2c_launch_f32(N, contig, sign, cfg, a, s) : c2c_launch_f64(N, contig, sign, cfg, a, s));

@@ -80,12 +80,16 @@ struct StageArgs {
     Side side[2];
     const Tile *tiles;
     const void *twiddle;  // N entries e^{-2 pi i m / N} (R2C/C2R: N/2-point table + N-point post table;
-                          // R2R: N-point table + e^{-i pi k / 2N}, k < N, in twiddle2)
+                          // R2R: N-point table + e^{-i pi k / 2N}, k < N, in twiddle2; mixed-radix
+                          // stages: L = N or M entries here, the chirp e^{-pi i m^2 / N} in twiddle2)
     const void *twiddle2;
+    const void *twiddle3;  // mixed-radix stage with Bluestein: DFT_M of the conjugate chirp (M entries)
     int64_t ntiles;
     double scale;
     int32_t N;      // positions per line on the complex side (C2C/COPY); real length for R2C/C2R
     int32_t flags;
+    int32_t M;      // mixed-radix stage: Bluestein convolution length (0: direct plan)
+    int32_t reserved;
 };
 
 }  // namespace pfft

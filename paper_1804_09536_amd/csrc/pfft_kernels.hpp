@@ -15,7 +15,7 @@ struct KernelConfig {
     int W = 0;
     int threads = 0;
     int id = 0;        // tile-shape variant (0 default, 1 half, 2 double, 3 double in two LDS portions);
-                       // -1: direct-sum DFT kernel (lengths without a radix plan)
+                       // -1: LDS mixed-radix kernel (lengths without a register radix plan)
     int resident = 0;  // 1: grid = resident workgroups looping over tiles; 0: one tile per workgroup
 };
 
@@ -41,9 +41,15 @@ hipError_t c2c_launch_multi_f64(int N, int contig, int sign, const KernelConfig 
 int copy_config(int N, KernelConfig *cfg);
 hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg);
-int dft_config(int prec, int N, int kind, KernelConfig *cfg);
-hipError_t dft_launch(int prec, int N, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
-                      hipStream_t s);
+// Mixed-radix stages (k_mixed.hip): lines of any length that fits one
+// workgroup's LDS; lines whose largest prime factor exceeds kBluesteinPrime
+// run Bluestein's convolution of length mixed_bluestein_length(N) (7-smooth,
+// >= 2N-1; 0 for the direct plan, -1 if too long).
+constexpr int kBluesteinPrime = 32;
+int mixed_bluestein_length(int N);
+int mixed_config(int prec, int N, int kind, KernelConfig *cfg);
+hipError_t mixed_launch(int prec, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
+                        hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int r2r_config_f32(int N, int contig, int variant, KernelConfig *cfg);
 int r2r_config_f64(int N, int contig, int variant, KernelConfig *cfg);

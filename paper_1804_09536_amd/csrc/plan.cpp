@@ -13,6 +13,7 @@
 #include <array>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -158,7 +159,8 @@ struct Launch {
     int64_t ntiles = 0;
     size_t off_pos[2] = {0, 0}, off_na[2] = {0, 0}, off_rank[2] = {0, 0};
     int32_t R[2] = {0, 0};
-    size_t off_tw = 0, off_tw2 = 0;
+    size_t off_tw = 0, off_tw2 = 0, off_tw3 = 0;
+    int M = 0;             // mixed-radix stage: Bluestein convolution length (0: direct plan)
     KernelConfig cfg{};
 };
 
@@ -184,6 +186,7 @@ struct pfft_plan_s {
     std::vector<uint8_t> blob;
     std::map<std::pair<int, int>, std::array<size_t, 3>> side_cache;
     std::map<int, std::pair<size_t, size_t>> tw_cache;
+    std::map<std::pair<int, int>, size_t> aux_cache;  // (table kind, length) -> blob offset
     pfft_tuning tuning{};  // performance knobs (kernel tile variants, grid policy)
     std::vector<int> chain_in;  // creation arguments kept for rebuilding
     bool has_chain = false;
@@ -297,6 +300,89 @@ static size_t r2r_post_table(pfft_plan_s *p, int N)
         off = blob_put(p, t.data(), t.size() * 8);
     }
     p->tw_cache[-N] = {off, 0};
+    return off;
+}
+
+// The chirp e^{-pi i m^2 / N}, m < N, of Bluestein's identity, with the
+// angle reduced exactly (m^2 mod 2N) before the FP64 cos/sin.
+static size_t chirp_table(pfft_plan_s *p, int N)
+{
+    auto key = std::make_pair(1, N);
+    auto it = p->aux_cache.find(key);
+    if (it != p->aux_cache.end()) return it->second;
+    std::vector<double> t(2 * (size_t)N);
+    for (int64_t m = 0; m < N; m++) {
+        const double a = M_PI * (double)((m * m) % (2 * (int64_t)N)) / (double)N;
+        t[2 * m] = cos(a);
+        t[2 * m + 1] = -sin(a);
+    }
+    size_t off;
+    if (p->precision == PFFT_F32) {
+        std::vector<float> f(t.begin(), t.end());
+        off = blob_put(p, f.data(), f.size() * 4);
+    } else {
+        off = blob_put(p, t.data(), t.size() * 8);
+    }
+    p->aux_cache[key] = off;
+    return off;
+}
+
+// Host DFT in FP64 (Cooley-Tukey over the smallest prime factor, used only
+// for plan-time tables): x <- sum_j x_j e^{-2 pi i jk / n}.
+static void host_dft(std::vector<std::complex<double>> &x)
+{
+    const int64_t n = (int64_t)x.size();
+    if (n < 2) return;
+    int64_t f = n;
+    for (int64_t d = 2; d * d <= n; d++)
+        if (n % d == 0) {
+            f = d;
+            break;
+        }
+    const int64_t m = n / f;
+    std::vector<std::vector<std::complex<double>>> sub((size_t)f, std::vector<std::complex<double>>((size_t)m));
+    for (int64_t r = 0; r < f; r++) {
+        for (int64_t j = 0; j < m; j++) sub[r][j] = x[(size_t)(r + f * j)];
+        if (m > 1) host_dft(sub[r]);
+    }
+    for (int64_t k = 0; k < n; k++) {
+        std::complex<double> acc = 0.0;
+        for (int64_t r = 0; r < f; r++) {
+            const double a = 2.0 * M_PI * (double)((r * k) % n) / (double)n;
+            acc += std::complex<double>(cos(a), -sin(a)) * sub[r][(size_t)(k % m)];
+        }
+        x[(size_t)k] = acc;
+    }
+}
+
+// Bluestein's kernel for length N and convolution length M: the M-point DFT
+// of v, v_m = e^{+pi i m^2 / N} for |m| < N placed at m mod M, zero elsewhere.
+static size_t bluestein_table(pfft_plan_s *p, int N, int M)
+{
+    auto key = std::make_pair(2, N);
+    auto it = p->aux_cache.find(key);
+    if (it != p->aux_cache.end()) return it->second;
+    std::vector<std::complex<double>> v((size_t)M, 0.0);
+    for (int64_t m = 0; m < N; m++) {
+        const double a = M_PI * (double)((m * m) % (2 * (int64_t)N)) / (double)N;
+        const std::complex<double> c(cos(a), sin(a));
+        v[(size_t)m] = c;
+        if (m > 0) v[(size_t)(M - m)] = c;
+    }
+    host_dft(v);
+    std::vector<double> t(2 * (size_t)M);
+    for (int64_t k = 0; k < M; k++) {
+        t[2 * k] = v[(size_t)k].real();
+        t[2 * k + 1] = v[(size_t)k].imag();
+    }
+    size_t off;
+    if (p->precision == PFFT_F32) {
+        std::vector<float> f(t.begin(), t.end());
+        off = blob_put(p, f.data(), f.size() * 4);
+    } else {
+        off = blob_put(p, t.data(), t.size() * 8);
+    }
+    p->aux_cache[key] = off;
     return off;
 }
 
@@ -546,12 +632,28 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     if (variant == 5) variant = (ln.contig || ln.kind == KIND_R2R) ? 1 : (ln.N >= 1024 ? 4 : 3);
     int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
     if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
-    if (rc != 0)
-        return fail(PFFT_EUNSUPPORTED, "no kernel for length " + std::to_string(ln.N) +
-                                           (ln.contig ? " (contiguous)" : " (strided)"));
+    if (rc != 0) {
+        if (ln.kind == KIND_R2R)
+            return fail(PFFT_EUNSUPPORTED, "no real-to-real kernel for length " + std::to_string(ln.N) +
+                                               " (needs 2^a <= 4096 or 3*2^a <= 3072)");
+        const int M = mixed_bluestein_length(ln.N);
+        return fail(PFFT_EUNSUPPORTED, "length " + std::to_string(ln.N) + ": the line" +
+                                           (M > 0 ? " (through Bluestein's convolution of length " + std::to_string(M) + ")"
+                                                  : std::string()) +
+                                           " does not fit one workgroup's LDS");
+    }
     const int sides[2] = {ln.src, ln.dst};
     for (int s = 0; s < 2; s++) side_tables(p, sides[s], ln.axis, &ln.off_pos[s], &ln.off_na[s], &ln.off_rank[s], &ln.R[s]);
-    if (ln.kind == KIND_C2C) {
+    if (ln.cfg.id < 0 && ln.kind != KIND_COPY && ln.kind != KIND_R2R) {
+        // mixed-radix stage: the L-point table, and Bluestein's chirp and kernel
+        const int M = mixed_bluestein_length(ln.N);
+        ln.M = M > 0 ? M : 0;
+        ln.off_tw = twiddle_table(p, M > 0 ? M : ln.N);
+        if (M > 0) {
+            ln.off_tw2 = chirp_table(p, ln.N);
+            ln.off_tw3 = bluestein_table(p, ln.N, M);
+        }
+    } else if (ln.kind == KIND_C2C) {
         ln.off_tw = twiddle_table(p, ln.N);
     } else if (ln.kind == KIND_R2C || ln.kind == KIND_C2R) {
         ln.off_tw = twiddle_table(p, ln.N / 2 > 0 ? ln.N / 2 : 1);
@@ -859,6 +961,8 @@ static StageArgs stage_args(const pfft_plan_s *p, const Launch &ln, const uint8_
     a.tiles = (const Tile *)(dev + ln.off_tiles);
     a.twiddle = dev + ln.off_tw;
     a.twiddle2 = dev + ln.off_tw2;
+    a.twiddle3 = dev + ln.off_tw3;
+    a.M = ln.M;
     a.ntiles = ln.ntiles;
     a.scale = scale;
     a.N = ln.N;
@@ -1441,6 +1545,7 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
     plan->blob.clear();
     plan->side_cache.clear();
     plan->tw_cache.clear();
+    plan->aux_cache.clear();
     plan->real0 = -1;
     plan->dev = nullptr;
     const int n = (int)plan->chain_in.size() / 2;

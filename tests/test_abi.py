@@ -81,7 +81,7 @@ def test_error_codes():
     assert _create((16, 16, 16), (2,), chain=[(3, 1)]) == -3   # no such direction
     assert _create((16, 16, 16), (4,), chain=[]) == -3          # axis 0 never whole
     assert _create((16, 16, 17), (2, 2)) == 0                   # direct-sum DFT kernel
-    assert _create((4, 4, 10247), (2, 2)) == -5                 # prime, too long for the DFT's LDS
+    assert _create((4, 4, 10247), (2, 2)) == -5                 # prime: its Bluestein convolution (20580) exceeds the LDS
     assert _create((4, 4, 10247), (2, 2), flags=4) == 0         # layouts only: any length
     assert _create((16, 16, 16), (2, 2), flags=1 << 7) == -1    # unknown flag bit
 
