@@ -45,6 +45,9 @@ WORKLOADS = {
     # real-to-real: type II cosine transform on every axis (type III back)
     "dct512": ((512, 512, 512), (8, 8), "r2r", "f32", None),
     "c2c4d64": ((64, 64, 64, 64), (2, 2, 4), "c2c", "f32", None),
+    # the transposed-out alignment of the output (split axes stored first)
+    "slab512_tr": ((512, 512, 512), (8,), "c2c", "f32", None, {"transposed_out": True}),
+    "pencil512_tr": ((512, 512, 512), (8, 8), "c2c", "f32", None, {"transposed_out": True}),
 }
 
 KIND_NAMES = {"c2c": "c2c_stage", "copy": "redistribute_copy", "r2c": "r2c_stage", "c2r": "c2r_stage",
@@ -285,10 +288,11 @@ def measure_plain(name, steps, warmup, path="fused", placement=None, profile=Tru
     from paper_1804_09536_amd import inputs
     from paper_1804_09536_amd.plan import Plan
 
-    shape, grid, kind, prec, chain = WORKLOADS[name]
+    shape, grid, kind, prec, chain = WORKLOADS[name][:5]
+    extra = WORKLOADS[name][5] if len(WORKLOADS[name]) > 5 else {}
     dev = torch.device("cuda:0")
     plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=path, device=dev,
-                placement=placement).bind()
+                placement=placement, **extra).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
     # arrays beyond 2^28 elements are drawn on the device (no host copy, no CPU baseline)
     big = n_in > (1 << 28)

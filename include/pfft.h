@@ -107,6 +107,16 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
    layout (it then runs in place), an R2C plan one spectrum-sized buffer instead of two.  `in` and
    `out` must not overlap.  A real input is never written. */
 #define PFFT_DESTROY_INPUT (1u << 8)
+/* Transposed output (Sec. 3.2.1, Eq. fftw_transposed_out): every rank's block of the last layout of
+   the chain (the forward output, the backward input) is stored with its split axes first, in
+   grid-direction order, then its whole axes in increasing order; the slab (N0/P, N1, N2) ->
+   (N1/P, N0, N2) of the paper, a pencil (N0, N1/P0, N2/P1) -> (N1/P0, N2/P1, N0).  The global index of
+   every element and the blocks' extents and starts are unchanged (pfft_local_block reports them per
+   axis); pfft_layout_axis_order gives each layout's storage order.  Not for PFFT_R2R plans.  On
+   grids of two or more directions the forward placement GATHER with the backward placement
+   BWD_SCATTER keeps every stage on the register kernels (others leave a stage whose lines are
+   adjacent along different indices on its two sides, which runs one line per tile). */
+#define PFFT_TRANSPOSED_OUT (1u << 9)
 
 /* status codes */
 #define PFFT_OK 0
@@ -137,7 +147,8 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
  *   nsteps: number of chain steps (ignored when chain is NULL).
  *   flags: PFFT_PATH_* (selects how redistributions are executed), optionally
  *     or-ed with one forward and one backward placement (PFFT_PLACE_*,
- *     PFFT_PLACE_BWD_*), PFFT_DESTROY_INPUT and PFFT_LAYOUTS_ONLY.
+ *     PFFT_PLACE_BWD_*), PFFT_DESTROY_INPUT, PFFT_TRANSPOSED_OUT and
+ *     PFFT_LAYOUTS_ONLY.
  * The chain must leave every axis transformed (each axis whole in some
  * layout).  For PFFT_R2C the last axis must be whole in layout 0.
  * Returns PFFT_OK and *out, or an error (then *out is NULL).
@@ -213,6 +224,11 @@ int pfft_num_layouts(pfft_plan plan, int *n);
  */
 int pfft_local_block(pfft_plan plan, int layout, int real, int rank, int64_t *shape, int64_t *start,
                      int64_t *offset);
+
+/* Storage order of every block of chain layout `layout`: order[k] (ndim ints) is the axis at
+   position k of the block's C-order index (the identity except for the last layout of a
+   PFFT_TRANSPOSED_OUT plan). */
+int pfft_layout_axis_order(pfft_plan plan, int layout, int *order);
 
 /* Bytes of a layout's buffer (real = as above). */
 int pfft_buffer_bytes(pfft_plan plan, int layout, int real, size_t *bytes);

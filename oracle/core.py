@@ -43,7 +43,7 @@ __all__ = [
     "redistribute_pairs", "fft_axis", "dft1", "bruteforce_dftn", "forward",
     "backward", "adjoint_forward", "adjoint_backward", "wavenumber_weight",
     "loss_and_grad", "Chain", "dft_bins", "layout_offset",
-    "R2R_KINDS", "r2r_matrix", "r2r_axis", "bruteforce_r2rn",
+    "R2R_KINDS", "r2r_matrix", "r2r_axis", "bruteforce_r2rn", "transposed_order", "relayout",
 ]
 
 
@@ -132,6 +132,11 @@ class Layout:
     shape: tuple
     grid: tuple
     axis_dir: tuple
+    order: tuple = None  # storage order of the blocks (axis at each C-order position); None = identity
+
+    @property
+    def storage(self) -> tuple:
+        return tuple(range(len(self.shape))) if self.order is None else tuple(self.order)
 
     @property
     def nranks(self) -> int:
@@ -155,7 +160,22 @@ class Layout:
         return int(np.prod(self.shape))
 
     def with_shape(self, shape):
-        return Layout(tuple(shape), self.grid, self.axis_dir)
+        return Layout(tuple(shape), self.grid, self.axis_dir, self.order)
+
+    def regular(self):
+        """The same alignment with blocks stored in C order of the axes."""
+        return Layout(self.shape, self.grid, self.axis_dir)
+
+
+def transposed_order(axis_dir):
+    """Storage order of a transposed-out alignment (Sec. 3.2.1, Eq.
+    fftw_transposed_out, where the slab (N0/P, N1, N2) becomes
+    (N1/P, N0, N2)): the split axes first, by grid direction, then the whole
+    axes in increasing order."""
+    nd = len(axis_dir)
+    ngrid = max([d for d in axis_dir if d >= 0] + [-1]) + 1
+    split = [m for d in range(ngrid) for m in range(nd) if axis_dir[m] == d]
+    return tuple(split + [m for m in range(nd) if axis_dir[m] < 0])
 
 
 def paper_layouts(ndim: int, ngrid: int):
@@ -211,13 +231,15 @@ def transform_schedule(chain_dirs):
 
 def scatter_global(glob: np.ndarray, lay: Layout) -> np.ndarray:
     """Cut a global C-order array into the rank blocks of ``lay`` by plain numpy
-    slicing, and concatenate them in rank order."""
+    slicing (each block's axes permuted into the layout's storage order), and
+    concatenate them in rank order."""
     assert tuple(glob.shape) == tuple(lay.shape)
     parts = []
+    order = lay.storage
     for r in range(lay.nranks):
         ls, st = lay.block(r)
         sl = tuple(slice(s, s + n) for s, n in zip(st, ls))
-        parts.append(np.ascontiguousarray(glob[sl]).reshape(-1))
+        parts.append(np.ascontiguousarray(np.transpose(glob[sl], order)).reshape(-1))
     return np.concatenate(parts) if parts else np.zeros(0, glob.dtype)
 
 
@@ -225,16 +247,28 @@ def gather_global(buf: np.ndarray, lay: Layout) -> np.ndarray:
     """Inverse of ``scatter_global``."""
     glob = np.empty(lay.shape, dtype=buf.dtype)
     offs = lay.offsets()
+    order = lay.storage
+    inverse = tuple(int(k) for k in np.argsort(order))
     for r in range(lay.nranks):
         ls, st = lay.block(r)
         sl = tuple(slice(s, s + n) for s, n in zip(st, ls))
-        glob[sl] = buf[offs[r]:offs[r + 1]].reshape(ls)
+        stored = buf[offs[r]:offs[r + 1]].reshape(tuple(ls[m] for m in order))
+        glob[sl] = np.transpose(stored, inverse)
     return glob
 
 
+def relayout(buf: np.ndarray, A: Layout, B: Layout) -> np.ndarray:
+    """The buffer of layout A rewritten in layout B (same global array):
+    gathered to the global array and cut again."""
+    return scatter_global(gather_global(buf, A), B)
+
+
 def redistribute(buf: np.ndarray, A: Layout, B: Layout) -> np.ndarray:
-    """Global-view redistribution (Eq. gt): out[B(g)] = in[A(g)] for every g."""
+    """Global-view redistribution (Eq. gt): out[B(g)] = in[A(g)] for every g.
+    Layouts with a non-C storage order go through ``relayout``."""
     assert A.shape == B.shape and A.grid == B.grid
+    if A.order is not None or B.order is not None:
+        return relayout(np.asarray(buf), A, B)
     buf = np.ascontiguousarray(buf)
     out = np.empty_like(buf)
     _load().oracle_redistribute_global(len(A.shape), _i64(A.shape), len(A.grid), _i64(A.grid),
@@ -300,7 +334,8 @@ def dft_bins(glob: np.ndarray, bins, sign: int, scale: float) -> np.ndarray:
 
 def layout_offset(lay: Layout, g) -> int:
     """Position of global index g in a layout's buffer (found by searching
-    each split axis's parts)."""
+    each split axis's parts; the local index is taken in the layout's
+    storage order)."""
     nd = len(lay.shape)
     coords = [0] * max(1, len(lay.grid))
     loc = [0] * nd
@@ -320,7 +355,7 @@ def layout_offset(lay: Layout, g) -> int:
         rank = rank * lay.grid[i] + c
     ls, _ = lay.block(rank)
     off = 0
-    for m in range(nd):
+    for m in lay.storage:
         off = off * ls[m] + loc[m]
     return lay.offsets()[rank] + off
 
@@ -444,9 +479,10 @@ class Chain:
     kind: str = "c2c"
     norm: str = "forward"
     r2r: tuple = None  # kind="r2r": the forward transform of each axis (R2R_KINDS)
+    transposed_out: bool = False  # last layout stored in the transposed-out order
 
     @staticmethod
-    def paper(shape, grid, kind="c2c", norm="forward", steps=None, r2r=None):
+    def paper(shape, grid, kind="c2c", norm="forward", steps=None, r2r=None, transposed_out=False):
         shape = tuple(int(x) for x in shape)
         grid = tuple(int(x) for x in grid)
         dirs = (paper_layouts(len(shape), len(grid)) if steps is None
@@ -455,7 +491,7 @@ class Chain:
             r2r = tuple(r2r) if r2r is not None else ("dct2",) * len(shape)
             if len(r2r) != len(shape) or any(k not in R2R_KINDS for k in r2r):
                 raise ValueError("one r2r kind per axis")
-        return Chain(shape, grid, dirs, kind, norm, r2r)
+        return Chain(shape, grid, dirs, kind, norm, r2r, bool(transposed_out))
 
     def spectral_shape(self):
         if self.kind == "r2c":
@@ -463,8 +499,13 @@ class Chain:
         return self.shape
 
     def layout(self, li: int, spectral: bool = True) -> Layout:
+        """Alignment li as stored (the last one in the transposed-out order
+        when the chain has it)."""
         shp = self.spectral_shape() if spectral else self.shape
-        return Layout(shp, self.grid, tuple(self.dirs[li]))
+        order = None
+        if self.transposed_out and li == len(self.dirs) - 1 and spectral:
+            order = transposed_order(self.dirs[li])
+        return Layout(shp, self.grid, tuple(self.dirs[li]), order)
 
     def input_layout(self) -> Layout:
         return self.layout(0, spectral=(self.kind != "r2c"))
@@ -480,6 +521,10 @@ class Chain:
         if self.norm == "backward":
             return 1.0 if direction == "forward" else 1.0 / n
         return 1.0
+
+
+def _regular(ch: Chain) -> Chain:
+    return Chain(ch.shape, ch.grid, ch.dirs, ch.kind, ch.norm, ch.r2r, False)
 
 
 def _run_forward(ch: Chain, buf, sign, scale_of, r2c_mode):
@@ -538,29 +583,48 @@ def _run_backward(ch: Chain, buf, sign, scale_of, halve):
     return data
 
 
+def _to_stored(ch: Chain, out):
+    # the last layout as stored (transposed-out order) from its C-order form
+    if not ch.transposed_out:
+        return out
+    last = len(ch.dirs) - 1
+    return relayout(out, ch.layout(last).regular(), ch.layout(last))
+
+
+def _from_stored(ch: Chain, buf):
+    if not ch.transposed_out:
+        return buf
+    last = len(ch.dirs) - 1
+    return relayout(np.asarray(buf), ch.layout(last), ch.layout(last).regular())
+
+
 def forward(ch: Chain, buf: np.ndarray) -> np.ndarray:
     """Distributed forward transform (Eq. fftn_forward with the chain's
     redistributions, e.g. Eqs. pencil0-pencil2): input in layout 0, output in
-    the last layout."""
-    return _run_forward(ch, buf, -1, lambda a: ch.scale(a, "forward"), "r2c")
+    the last layout (as stored)."""
+    reg = _regular(ch)
+    return _to_stored(ch, _run_forward(reg, buf, -1, lambda a: ch.scale(a, "forward"), "r2c"))
 
 
 def backward(ch: Chain, buf: np.ndarray) -> np.ndarray:
     """Distributed backward transform (Eq. fftn_backward): the mirror chain."""
-    return _run_backward(ch, buf, +1, lambda a: ch.scale(a, "backward"), False)
+    reg = _regular(ch)
+    return _run_backward(reg, _from_stored(ch, buf), +1, lambda a: ch.scale(a, "backward"), False)
 
 
 def adjoint_forward(ch: Chain, buf: np.ndarray) -> np.ndarray:
     """Adjoint of ``forward`` under the real inner product Re<a, b>: reversed
     chain, inverse redistributions, sign +, the forward's per-axis factors.
     For r2c, Re(F^H S^T z): interior bins halved before the c2r."""
-    return _run_backward(ch, buf, +1, lambda a: ch.scale(a, "forward"), True)
+    reg = _regular(ch)
+    return _run_backward(reg, _from_stored(ch, buf), +1, lambda a: ch.scale(a, "forward"), True)
 
 
 def adjoint_backward(ch: Chain, buf: np.ndarray) -> np.ndarray:
     """Adjoint of ``backward``: forward chain with sign -, the backward's
     factors; for r2c the c2r's adjoint is an r2c with interior bins doubled."""
-    return _run_forward(ch, buf, -1, lambda a: ch.scale(a, "backward"), "r2c_double")
+    reg = _regular(ch)
+    return _to_stored(ch, _run_forward(reg, buf, -1, lambda a: ch.scale(a, "backward"), "r2c_double"))
 
 
 def wavenumber_weight(spectral_shape, real_last: bool, real_n: int = None, hermitian: bool = True) -> np.ndarray:

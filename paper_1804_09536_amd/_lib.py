@@ -20,6 +20,7 @@ PATHS = {"fused": 0, "unfused": 1, "pack_realign": 2}
 PFFT_LAYOUTS_ONLY = 4
 PFFT_PLACE_SCATTER = 8
 PFFT_DESTROY_INPUT = 1 << 8
+PFFT_TRANSPOSED_OUT = 1 << 9
 ENERGY_PARTIALS = 1024  # PFFT_ENERGY_PARTIALS: FP64 scratch of pfft_weighted_energy
 PLACEMENTS = {"gather": 0, "scatter": 1, "direct": 2, "final": 3}
 
@@ -69,6 +70,7 @@ def load():
         "pfft_validate_plan": [vp],
         "pfft_num_layouts": [vp, ip],
         "pfft_local_block": [vp, c_int, c_int, c_int, i64p, i64p, i64p],
+        "pfft_layout_axis_order": [vp, c_int, ip],
         "pfft_buffer_bytes": [vp, c_int, c_int, ctypes.POINTER(sz)],
         "pfft_device_state_bytes": [vp, ctypes.POINTER(sz)],
         "pfft_bind_device_state": [vp, vp, vp],

@@ -39,7 +39,7 @@ int launch_stage(int kind, int prec, int N, int contig, int sign, const KernelCo
                  const StageArgs &a, hipStream_t s)
 {
     if (cfg.id < 0 && kind != KIND_COPY && kind != KIND_R2R)
-        return (int)mixed_launch(prec, kind, contig, sign, cfg, a, s);
+        return (int)mixed_launch(prec, kind, sign, cfg, a, s);
     switch (kind) {
     case KIND_C2C:
         return (int)(prec == 0 ? c2c_launch_f32(N, contig, sign, cfg, a, s) : c2c_launch_f64(N, contig, sign, cfg, a, s));

@@ -55,8 +55,12 @@ struct C2CDefault {
 };
 
 // STREAM: strided tiles may use streaming loads / stores (SF_LOAD_NT,
-// SF_STORE_NT); without it those paths are not generated.
-template <typename T, int N, bool CONTIG, int SIGN, class S, bool STREAM = true>
+// SF_STORE_NT); without it those paths are not generated.  XS: the
+// destination's lines step the other way (a stage into or out of a layout
+// with another storage order: lines adjacent on one side, each line
+// contiguous on the other); loads keep the kernel's mode, stores go point by
+// point to line w at O + w (strided kernels) or I + w (contiguous kernels).
+template <typename T, int N, bool CONTIG, int SIGN, class S, bool STREAM = true, bool XS = false>
 struct C2CWorker {
     using T2 = typename V2<T>::type;
     using T4 = typename V2<T>::quad;
@@ -136,7 +140,7 @@ struct C2CWorker {
         if (!fast) count = -count;  // sign marks the predicated path for process()
         SideAddr<P> src;
         src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
-        dst.init(a.side[1], t, 1, jt, TPL, N, CONTIG);
+        dst.init(a.side[1], t, 1, jt, TPL, N, XS ? !CONTIG : CONTIG);
         const T2 *__restrict__ in = (const T2 *)a.src;
         int lo[NL];
         if constexpr (!CONTIG) line_offsets(t, 0, lo);
@@ -190,6 +194,18 @@ struct C2CWorker {
                 for (int m = 0; m < P; m++) v[l][m] = c_scale(v[l][m], scale);
         }
         T2 *__restrict__ out = (T2 *)a.dst;
+        if constexpr (XS) {
+            // line w of the destination at dst.off[m] + w * dst.stride[m]
+            const int cnt = count > 0 ? count : -count;
+#pragma unroll
+            for (int l = 0; l < NL; l++) {
+                const bool ok = wl[l] < cnt;
+#pragma unroll
+                for (int m = 0; m < P; m++)
+                    if (ok) out[dst.off[m] + wl[l] * dst.stride[m]] = v[l][m];
+            }
+            return;
+        }
         // Whole destination lines along the last axis are written with
         // streaming stores (measured faster); rows of strided tiles and line
         // segments scattered over several blocks with ordinary stores.
@@ -273,11 +289,11 @@ struct TwiddleStage {
 // `tiles` is a.tiles passed as a restrict-qualified argument: tile records
 // are then known to be unchanged by the kernel's stores and can be read
 // through the scalar cache.
-template <typename T, int N, bool CONTIG, int SIGN, class S>
+template <typename T, int N, bool CONTIG, int SIGN, class S, bool XS = false>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c(
     StageArgs a, const Tile *__restrict__ tiles)
 {
-    using Wk = C2CWorker<T, N, CONTIG, SIGN, S>;
+    using Wk = C2CWorker<T, N, CONTIG, SIGN, S, true, XS>;
     using T2 = typename Wk::T2;
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];

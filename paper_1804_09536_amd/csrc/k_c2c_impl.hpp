@@ -56,6 +56,24 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
     return hipGetLastError();
 }
 
+// The stage whose destination lines step the other way (XS), with the
+// measured default tile shape of the kernel's mode.
+template <typename T, int N, bool CONTIG>
+struct C2CXsShape {
+    static constexpr int V = C2CVariant<T, N, CONTIG, CONTIG ? 1 : 3>::exists ? (CONTIG ? 1 : 3) : 0;
+    using type = typename C2CVariant<T, N, CONTIG, V>::type;
+};
+
+template <typename T, int N, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_xs(const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    using S = typename C2CXsShape<T, N, CONTIG>::type;
+    (void)c;
+    long g = a.ntiles < 1 ? 1 : a.ntiles;
+    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S, true>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
 template <typename T, int N, bool CONTIG, int SIGN, int V>
 static hipError_t c2c_launch_multi_v(const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
                                      hipStream_t s)
@@ -101,6 +119,7 @@ static hipError_t c2c_launch_multi_s(const KernelConfig &c, const StageArgs *arg
 template <typename T, int N, bool CONTIG, int SIGN>
 static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
+    if (c.xside) return c2c_launch_xs<T, N, CONTIG, SIGN>(c, a, s);
     switch (c.id) {
     case 1:
         if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
@@ -123,6 +142,13 @@ template <typename T, int N, bool CONTIG>
 static void c2c_cfg_mode(int variant, KernelConfig *c)
 {
     int W, NT, id;
+    if (variant == 6) {  // the XS stage's shape
+        c->W = C2CXsShape<T, N, CONTIG>::type::W;
+        c->threads = C2CXsShape<T, N, CONTIG>::type::NT;
+        c->id = C2CXsShape<T, N, CONTIG>::V;
+        c->xside = 1;
+        return;
+    }
     if (variant == 1 && C2CVariant<T, N, CONTIG, 1>::exists) {
         W = C2CVariant<T, N, CONTIG, 1>::type::W;
         NT = C2CVariant<T, N, CONTIG, 1>::type::NT;

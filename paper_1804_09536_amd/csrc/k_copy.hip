@@ -26,8 +26,9 @@ __global__ __launch_bounds__(kCopyThreads) void k_copy(StageArgs a, int TPL)
     E *__restrict__ out = (E *)a.dst;
     for (int j0 = 0; j0 < N; j0 += TPL * kCopyUnroll) {
         SideAddr<kCopyUnroll> s, d;
-        s.init(a.side[0], t, 0, j0 + jt, TPL, N, true);
-        d.init(a.side[1], t, 1, j0 + jt, TPL, N, true);
+        // lines step in O (contiguous lines) unless the tile says I on that side
+        s.init(a.side[0], t, 0, j0 + jt, TPL, N, !(t.flags & 4));
+        d.init(a.side[1], t, 1, j0 + jt, TPL, N, !(t.flags & 8));
         bool ok[kCopyUnroll];
 #pragma unroll
         for (int u = 0; u < kCopyUnroll; u++) ok[u] = j0 + jt + u * TPL < N;

@@ -45,13 +45,15 @@ constexpr int kMixedMaxLds = 160 * 1024;
 #define PFFT_C73 -0.90096886790241912624
 #define PFFT_S73 0.43388373911755812048
 
-// Element (line w, position j) of a tile on side s.
-__device__ __forceinline__ long mixed_addr(const Side &sd, const Tile &t, int s, int w, int j, bool contig)
+// Element (line w, position j) of a tile on side s; the tile's flag bit 2+s
+// says whether its lines step in I (adjacent lines) or in O (contiguous lines).
+__device__ __forceinline__ long mixed_addr(const Side &sd, const Tile &t, int s, int w, int j)
 {
+    const bool istep = (t.flags >> (2 + s)) & 1;
     const int2 pc = sd.pos[j];
     const long na = sd.na[pc.x];
     const long base = sd.rank_off[t.rank[s] + pc.x * sd.R];
-    const long O = t.O[s] + (contig ? w : 0), I = t.I[s] + (contig ? 0 : w);
+    const long O = t.O[s] + (istep ? 0 : w), I = t.I[s] + (istep ? w : 0);
     return base + (O * na + pc.y) * t.E[s] + I;
 }
 
@@ -226,8 +228,7 @@ __device__ void mixed_transform(typename V2<T>::type *a, typename V2<T>::type *b
 }
 
 template <typename T, int KIND>
-__global__ __launch_bounds__(kMixedThreads) void k_mixed(StageArgs a, const Tile *__restrict__ tiles, int sign,
-                                                         int contig, int W)
+__global__ __launch_bounds__(kMixedThreads) void k_mixed(StageArgs a, const Tile *__restrict__ tiles, int sign, int W)
 {
     using T2 = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -246,12 +247,15 @@ __global__ __launch_bounds__(kMixedThreads) void k_mixed(StageArgs a, const Tile
     const T2 *__restrict__ vhat = (const T2 *)a.twiddle3;   // M entries, sign -1
     const T sg = (T)sign;
     const bool halve = (a.flags & SF_HALVE_INTERIOR) != 0;
-    // load (and zero the Bluestein padding / the C2R extension)
+    // load (and zero the Bluestein padding / the C2R extension); where the
+    // source lines are adjacent (step in I) consecutive threads take
+    // consecutive lines, else consecutive positions of a line
+    const bool in_across = (t.flags >> 2) & 1;
     for (int e = threadIdx.x; e < count * L; e += kMixedThreads) {
-        const int w = e / L, j = e - w * L;
+        const int w = in_across ? e % count : e / L, j = in_across ? e / count : e - (e / L) * L;
         T2 x = c_zero<T2>();
         if (KIND == KIND_C2R ? j < H : j < N) {
-            const long ad = mixed_addr(a.side[0], t, 0, w, j, contig != 0);
+            const long ad = mixed_addr(a.side[0], t, 0, w, j);
             if constexpr (KIND == KIND_R2C) {
                 x.x = ((const T *)a.src)[ad];
             } else {
@@ -308,15 +312,16 @@ __global__ __launch_bounds__(kMixedThreads) void k_mixed(StageArgs a, const Tile
     }
     const T scale = (T)a.scale * (M > 0 ? (T)1 / (T)M : (T)1);
     const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
+    const bool out_across = (t.flags >> 3) & 1;
     for (int e = threadIdx.x; e < count * nout; e += kMixedThreads) {
-        const int w = e / nout, k = e - w * nout;
+        const int w = out_across ? e % count : e / nout, k = out_across ? e / count : e - (e / nout) * nout;
         T2 y = res[(long)w * L + k];
         if (M > 0) {
             T2 c = chirp[k];
             c.y *= -sg;
             y = c_mul(y, c);
         }
-        const long ad = mixed_addr(a.side[1], t, 1, w, k, contig != 0);
+        const long ad = mixed_addr(a.side[1], t, 1, w, k);
         if constexpr (KIND == KIND_C2R) {
             ((T *)a.dst)[ad] = y.x * scale;
         } else {
@@ -383,13 +388,12 @@ int mixed_config(int prec, int N, int kind, KernelConfig *cfg)
     return 0;
 }
 
-hipError_t mixed_launch(int prec, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
-                        hipStream_t s)
+hipError_t mixed_launch(int prec, int kind, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s)
 {
     const size_t lds = mixed_lds(prec, a.M > 0 ? a.M : a.N, cfg.W);
     if (lds > 64 * 1024 && mixed_prepare() != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.ntiles), block(kMixedThreads);
-#define PFFT_MIXED(T, K) hipLaunchKernelGGL((k_mixed<T, K>), grid, block, lds, s, a, a.tiles, sign, contig, cfg.W)
+#define PFFT_MIXED(T, K) hipLaunchKernelGGL((k_mixed<T, K>), grid, block, lds, s, a, a.tiles, sign, cfg.W)
     if (prec == 0) {
         if (kind == KIND_C2C) PFFT_MIXED(float, KIND_C2C);
         else if (kind == KIND_R2C) PFFT_MIXED(float, KIND_R2C);

@@ -17,6 +17,7 @@ struct KernelConfig {
     int id = 0;        // tile-shape variant (0 default, 1 half, 2 double, 3 double in two LDS portions);
                        // -1: LDS mixed-radix kernel (lengths without a register radix plan)
     int resident = 0;  // 1: grid = resident workgroups looping over tiles; 0: one tile per workgroup
+    int xside = 0;     // complex stage whose destination lines step the other way (variant 6)
 };
 
 // Fills cfg for a stage kernel (kind: StageKind; prec: 0 = f32, 1 = f64;
@@ -48,8 +49,7 @@ int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg);
 constexpr int kBluesteinPrime = 32;
 int mixed_bluestein_length(int N);
 int mixed_config(int prec, int N, int kind, KernelConfig *cfg);
-hipError_t mixed_launch(int prec, int kind, int contig, int sign, const KernelConfig &cfg, const StageArgs &a,
-                        hipStream_t s);
+hipError_t mixed_launch(int prec, int kind, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 int r2r_config_f32(int N, int contig, int variant, KernelConfig *cfg);
 int r2r_config_f64(int N, int contig, int variant, KernelConfig *cfg);

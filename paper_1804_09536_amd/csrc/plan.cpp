@@ -58,15 +58,22 @@ struct Layout {
     std::vector<int64_t> rank_off;   // P+1 prefix sums of block sizes
     std::vector<int32_t> own[kMaxDims], loc[kMaxDims];
     std::vector<int64_t> dir_n[kMaxDims];  // per direction d and coordinate c: local extent of the axis d splits
+    // Storage order of every rank's block: order[k] is the axis at position k
+    // of the block's C-order index (identity for the paper's layouts; the
+    // transposed output layout stores its split axes first), pos_of its inverse.
+    int order[kMaxDims] = {};
+    int pos_of[kMaxDims] = {};
 
-    void init(int nd, const int64_t *shp, int ng, const int64_t *grd, const int *dirs)
+    void init(int nd, const int64_t *shp, int ng, const int64_t *grd, const int *dirs, const int *ord = nullptr)
     {
         ndim = nd;
         ngrid = ng;
         for (int m = 0; m < nd; m++) {
             shape[m] = shp[m];
             axis_dir[m] = dirs[m];
+            order[m] = ord ? ord[m] : m;
         }
+        for (int k = 0; k < nd; k++) pos_of[order[k]] = k;
         P = 1;
         for (int i = 0; i < ng; i++) {
             grid[i] = grd[i];
@@ -154,6 +161,7 @@ struct Launch {
     int sine = 0;          // R2R: sine (1) or cosine (0) transform
     int xcd = 0;           // complex strided stage whose tiles go to the XCDs in contiguous ranges
     int stream = 0;        // complex strided stage: bit 0 streaming loads, bit 1 streaming stores
+    int mixed_sides = 0;   // transform axis stored last on one side only (into / out of a transposed layout)
     // device blob offsets
     size_t off_tiles = 0;
     int64_t ntiles = 0;
@@ -425,12 +433,17 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
                 if (m != a && L.axis_dir[m] >= 0) c[L.axis_dir[m]] = L.own[m][g[m]];
             int64_t rank = 0;
             for (int i = 0; i < L.ngrid; i++) rank += c[i] * L.rstride[i];
+            // outer index over the axes stored before the transform axis,
+            // inner index and extent over those stored after it
             int64_t O = 0, E = 1, I = 0;
-            for (int m = 0; m < a; m++) {
+            const int pa = L.pos_of[a];
+            for (int k = 0; k < pa; k++) {
+                const int m = L.order[k];
                 int64_t n = L.local_extent(m, L.axis_dir[m] >= 0 ? c[L.axis_dir[m]] : 0);
                 O = O * n + L.loc[m][g[m]];
             }
-            for (int m = a + 1; m < nd; m++) {
+            for (int k = pa + 1; k < nd; k++) {
+                const int m = L.order[k];
                 int64_t n = L.local_extent(m, L.axis_dir[m] >= 0 ? c[L.axis_dir[m]] : 0);
                 I = I * n + L.loc[m][g[m]];
                 E *= n;
@@ -443,11 +456,22 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
         lines.push_back(rec);
     }
     const bool contig = ln.contig != 0;
-    auto less = [contig](const LineRec &x, const LineRec &y) {
+    // lines of a tile step in I on a side where the transform axis is not
+    // stored last (the lines are adjacent there), in O where it is (each line
+    // is contiguous); the two sides differ only on a stage into or out of a
+    // layout with another storage order, which runs the LDS kernel
+    bool istep[2];
+    for (int s = 0; s < 2; s++) istep[s] = S[s]->pos_of[a] != nd - 1;
+    const bool mixed_sides = istep[0] != istep[1];
+    auto less = [contig, mixed_sides](const LineRec &x, const LineRec &y) {
         if (x.rank[1] != y.rank[1]) return x.rank[1] < y.rank[1];
         if (x.rank[0] != y.rank[0]) return x.rank[0] < y.rank[0];
         if (x.E[1] != y.E[1]) return x.E[1] < y.E[1];
         if (x.E[0] != y.E[0]) return x.E[0] < y.E[0];
+        if (mixed_sides) {
+            if (x.O[1] != y.O[1]) return x.O[1] < y.O[1];
+            return x.I[1] < y.I[1];
+        }
         if (contig) return x.O[1] < y.O[1];
         if (x.O[1] != y.O[1]) return x.O[1] < y.O[1];
         if (x.O[0] != y.O[0]) return x.O[0] < y.O[0];
@@ -456,15 +480,15 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
     std::sort(lines.begin(), lines.end(), less);
 
     // Runs: maximal sequences of lines that are adjacent on both sides (same
-    // ranks, inner extents and, in strided mode, outer index; consecutive O
-    // (contiguous mode) or I (strided mode)).
+    // ranks and inner extents; consecutive O with the same I where lines step
+    // in O, consecutive I with the same O where they step in I).
     std::vector<size_t> run_first;
     for (size_t i = 0; i < lines.size(); i++) {
         bool cont = i > 0;
         const LineRec &x = lines[i], &h = lines[i > 0 ? i - 1 : 0];
         for (int s = 0; s < 2 && cont; s++) {
             if (x.rank[s] != h.rank[s] || x.E[s] != h.E[s]) cont = false;
-            else if (contig) cont = (x.O[s] == h.O[s] + 1) && (x.I[s] == h.I[s]);
+            else if (!istep[s]) cont = (x.O[s] == h.O[s] + 1) && (x.I[s] == h.I[s]);
             else cont = (x.O[s] == h.O[s]) && (x.I[s] == h.I[s] + 1);
         }
         if (!cont) run_first.push_back(i);
@@ -575,6 +599,7 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
             quad = quad && (t.run % 4 == 0) && (t.b0 % 4 == 0) && (t.ostr[0] % 4 == 0) && (t.ostr[1] % 4 == 0);
         }
         for (int s = 0; s < 2 && !contig && (even || quad); s++) {
+            if (!istep[s]) continue;  // (a stage with mixed sides pairs lines on its adjacent side only)
             const Layout &L = *S[s];
             const int64_t npos = L.shape[a];
             const int d = L.axis_dir[a];
@@ -589,7 +614,8 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
                 if (addr & 3) quad = false;
             }
         }
-        t.flags = (even ? 1 : 0) | (quad ? 2 : 0);
+        // bits 2 / 3: the lines of side 0 / 1 step in I (else in O)
+        t.flags = (even ? 1 : 0) | (quad ? 2 : 0) | (istep[0] ? 4 : 0) | (istep[1] ? 8 : 0);
         tiles.push_back(t);
     }
     ln.ntiles = (int64_t)tiles.size();
@@ -610,10 +636,11 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
                  : 0;
 }
 
-static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs)
+static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs,
+                      const int *order = nullptr)
 {
     Layout L;
-    L.init(p->ndim, shape, ngrid, grid, dirs);
+    L.init(p->ndim, shape, ngrid, grid, dirs, order);
     p->layouts.push_back(std::move(L));
     return (int)p->layouts.size() - 1;
 }
@@ -621,6 +648,11 @@ static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int
 static int finish_launch(pfft_plan_s *p, Launch &ln)
 {
     const int prec = p->precision;
+    if (ln.kind == KIND_COPY) {
+        const bool last_s = p->layouts[ln.src].pos_of[ln.axis] == p->ndim - 1;
+        const bool last_d = p->layouts[ln.dst].pos_of[ln.axis] == p->ndim - 1;
+        ln.mixed_sides = last_s != last_d;
+    }
     if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
         return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
     const pfft_tuning &tu = p->tuning;
@@ -630,7 +662,17 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     // 5: the measured choice per length (wider tiles for long strided lines;
     // real-to-real stages are fastest with more, smaller workgroups)
     if (variant == 5) variant = (ln.contig || ln.kind == KIND_R2R) ? 1 : (ln.N >= 1024 ? 4 : 3);
-    int rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
+    int rc;
+    if (ln.mixed_sides && ln.kind != KIND_COPY) {
+        // lines contiguous on one side and adjacent on the other: the stage
+        // kernel in the source's mode with the destination stepped the other
+        // way (or, for lengths without a register plan, the LDS kernel, which
+        // loads and stores each side in its own order)
+        ln.contig = p->layouts[ln.src].pos_of[ln.axis] == p->ndim - 1 ? 1 : 0;
+        rc = ln.kind == KIND_C2C ? kernel_config(ln.kind, prec, ln.N, ln.contig, 6, &ln.cfg) : -1;
+    } else {
+        rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
+    }
     if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0) {
         if (ln.kind == KIND_R2R)
@@ -666,7 +708,7 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         ln.off_tw2 = twiddle_table(p, 4 * ln.N);  // its first N entries are e^{-i pi k / 2N}
     }
     // runs shorter than a tile are chained only for the Stockham stage kernels
-    build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig);
+    build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig && !ln.mixed_sides);
     if (ln.kind == KIND_C2C && !ln.contig && tu.xcd_order != 0) ln.xcd = tu.xcd_order == 1 ? 1 : 0;
     // Streaming accesses on strided rows where source and destination
     // together exceed the 256 MB last-level cache (512^3 pencil stages -4..-7 %
@@ -763,7 +805,13 @@ static int build_direction(pfft_plan_s *p, const std::vector<std::array<int, 5>>
         Launch ln;
         ln.kind = kind;
         ln.axis = axis;
-        ln.contig = axis == p->ndim - 1;
+        {
+            // contiguous mode where the transform axis is stored last on both sides
+            const bool last_s = p->layouts[tsrc].pos_of[axis] == p->ndim - 1;
+            const bool last_d = p->layouts[tdst].pos_of[axis] == p->ndim - 1;
+            ln.contig = last_s && last_d;
+            ln.mixed_sides = last_s != last_d;
+        }
         ln.src = tsrc;
         ln.dst = tdst;
         ln.sign = sign;
@@ -831,7 +879,22 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
     int64_t spec[kMaxDims];
     for (int m = 0; m < nd; m++) spec[m] = p->shape[m];
     if (p->kind == PFFT_R2C) spec[nd - 1] = p->shape[nd - 1] / 2 + 1;
-    for (int li = 0; li < p->nlayouts; li++) add_layout(p, spec, ng, p->grid, p->dirs[li].data());
+    for (int li = 0; li < p->nlayouts; li++) {
+        int order[kMaxDims];
+        if ((p->flags & PFFT_TRANSPOSED_OUT) && li == p->nlayouts - 1) {
+            // transposed output: the split axes first, in grid-direction
+            // order, then the whole axes (slab: (N1/P, N0, N2), Eq. fftw_transposed_out)
+            int k = 0;
+            for (int d = 0; d < ng; d++)
+                for (int m = 0; m < nd; m++)
+                    if (p->dirs[li][m] == d) order[k++] = m;
+            for (int m = 0; m < nd; m++)
+                if (p->dirs[li][m] < 0) order[k++] = m;
+            add_layout(p, spec, ng, p->grid, p->dirs[li].data(), order);
+        } else {
+            add_layout(p, spec, ng, p->grid, p->dirs[li].data());
+        }
+    }
     if (p->kind == PFFT_R2C) p->real0 = add_layout(p, p->shape, ng, p->grid, p->dirs[0].data());
     p->elem = (p->precision == PFFT_F32 ? 8 : 16) / (p->kind == PFFT_R2R ? 2 : 1);
     p->spec_bytes = (size_t)p->layouts[0].total() * p->elem;
@@ -856,6 +919,8 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
         int li = p->sched[k].first, axis = p->sched[k].second;
         int dst = place(fwd_place, k, li, k + 1 < K ? p->sched[k + 1].first : last, last);
         int kind = (k == 0 && p->kind == PFFT_R2C) ? KIND_R2C : p->kind == PFFT_R2R ? KIND_R2R : KIND_C2C;
+        // the real-to-complex stage writes a layout stored in C order
+        if (kind == KIND_R2C && dst != li && p->layouts[dst].pos_of[nd - 1] != nd - 1) dst = li;
         fsteps.push_back({where, li, dst, axis, kind});
         where = dst;
     }
@@ -867,6 +932,9 @@ static int build_plan(pfft_plan_s *p, const int *chain, int nsteps)
         if (k == K - 1 && p->kind == PFFT_R2C) {
             kind = KIND_C2R;
             dst = p->real0;
+        } else if (k == K - 2 && p->kind == PFFT_R2C && p->layouts[dst].pos_of[nd - 1] != nd - 1) {
+            // the complex-to-real stage reads a layout stored in C order
+            dst = p->sched[0].first;
         }
         bsteps.push_back({where, li, dst, axis, kind});
         where = dst;
@@ -1174,6 +1242,9 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
         for (int64_t ti = t_begin; ti < t_end && !failed.load(std::memory_order_relaxed); ti++) {
             const Tile &t = tiles[ti];
             if (t.count < 1 || t.count > ln.cfg.W) return report(std::string(what) + ": tile count");
+            for (int s = 0; s < 2; s++)
+                if (((t.flags >> (2 + s)) & 1) != (S[s]->pos_of[ln.axis] != nd - 1 ? 1 : 0))
+                    return report(std::string(what) + ": line step flag");
             ad.assign((size_t)t.count * (size_t)jall * 2, -1);
             if (t.run < 0 || (t.run > 0 && (ln.contig || t.b0 < 0 || t.b0 >= t.run)))
                 return report(std::string(what) + ": tile run");
@@ -1196,8 +1267,8 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
                             const int64_t a1 = roff[s][rank] + (O * na[s][c] + loc) * t.E[s] + I;
                             if (a1 - a0 != (q % t.run) + (q / t.run) * (int64_t)t.ostr[s])
                                 return report(std::string(what) + ": run stride");
-                        } else if (ln.contig) {
-                            O += w;
+                        } else if (!((t.flags >> (2 + s)) & 1)) {
+                            O += w;  // lines step in O on this side
                         } else {
                             I += w;
                         }
@@ -1217,7 +1288,8 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
                             const int64_t *ls = &bls[s][(size_t)rank_of[s] * nd];
                             const int64_t *st = &bst[s][(size_t)rank_of[s] * nd];
                             int64_t e = addr[s] - roff[s][rank_of[s]];
-                            for (int m = nd - 1; m >= 0; m--) {
+                            for (int k = nd - 1; k >= 0; k--) {  // C order over the storage order
+                                const int m = S[s]->order[k];
                                 g[s][m] = st[m] + e % ls[m];
                                 e /= ls[m];
                             }
@@ -1238,6 +1310,7 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
                 for (int s = 0; s < 2; s++)
                     for (int w = 0; w < t.count; w++)
                         for (int64_t j = 0; j < npos[s]; j++) {
+                            if (ln.mixed_sides && !((t.flags >> (2 + s)) & 1)) break;  // claims the adjacent side only
                             const bool first = ln.contig ? (j % G == 0) : (w % G == 0 && w + G <= t.count);
                             if (!first) continue;
                             const int64_t a0 = ad[((size_t)w * (size_t)jall + (size_t)j) * 2 + (size_t)s];
@@ -1358,10 +1431,11 @@ static int batch_plan(pfft_batch_s *b)
                 if (k >= list.size()) continue;
                 const Launch &ln = list[k];
                 BatchGroup *g = nullptr;
-                const bool multi = ln.kind == KIND_C2C && ln.cfg.id >= 0;  // a multi-transform kernel exists
+                // a multi-transform kernel exists (not for stages whose sides step differently)
+                const bool multi = ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.cfg.xside;
                 if (multi)
                     for (auto &x : gs)
-                        if (x.kind == KIND_C2C && x.cfg.id >= 0 && x.N == ln.N && x.contig == ln.contig &&
+                        if (x.kind == KIND_C2C && x.cfg.id >= 0 && !x.cfg.xside && x.N == ln.N && x.contig == ln.contig &&
                             x.cfg.id == ln.cfg.id && x.cfg.resident == ln.cfg.resident)
                             g = &x;
                 if (!g) {
@@ -1376,7 +1450,7 @@ static int batch_plan(pfft_batch_s *b)
                 g->members.push_back(m);
             }
             for (auto &g : gs) {
-                if (g.kind == KIND_C2C && g.cfg.id >= 0) {
+                if (g.kind == KIND_C2C && g.cfg.id >= 0 && !g.cfg.xside) {
                     int64_t nt = 0;
                     for (int m : g.members) nt += (dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd)[k].ntiles;
                     if ((int64_t)g.members.size() >= (1 << 23)) return fail(PFFT_EINVAL, "too many batch members");
@@ -1408,7 +1482,7 @@ static void batch_fill_args(pfft_batch_s *b)
     const uint8_t *dev = (const uint8_t *)b->dev;
     for (int dir = 0; dir < 2; dir++) {
         for (auto &g : b->groups[dir]) {
-            if (g.kind != KIND_C2C || g.cfg.id < 0) continue;
+            if (g.kind != KIND_C2C || g.cfg.id < 0 || g.cfg.xside) continue;
             StageArgs *args = (StageArgs *)(b->blob.data() + g.off_args);
             for (size_t mi = 0; mi < g.members.size(); mi++) {
                 const int m = g.members[mi];
@@ -1473,10 +1547,12 @@ static int create_plan(pfft_plan *out, int ndim, const int64_t *global_shape, in
             if (r2r[m] != PFFT_DCT2 && r2r[m] != PFFT_DST2) return fail(PFFT_EDTYPE, "bad real-to-real kind");
     }
     if (norm < PFFT_NORM_FORWARD || norm > PFFT_NORM_NONE) return fail(PFFT_EINVAL, "bad norm");
-    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK | PFFT_DESTROY_INPUT)) !=
-            0 ||
+    if ((flags & ~(PFFT_PATH_MASK | PFFT_LAYOUTS_ONLY | PFFT_PLACE_MASK | PFFT_PLACE_BWD_MASK | PFFT_DESTROY_INPUT |
+                   PFFT_TRANSPOSED_OUT)) != 0 ||
         (flags & PFFT_PATH_MASK) == 3u)
         return fail(PFFT_EINVAL, "bad flags");
+    if ((flags & PFFT_TRANSPOSED_OUT) && kind == PFFT_R2R && !(flags & PFFT_LAYOUTS_ONLY))
+        return fail(PFFT_EUNSUPPORTED, "transposed output is not available for real-to-real plans");
     if (chain && nsteps < 0) return fail(PFFT_EINVAL, "bad nsteps");
     int64_t total = 1;
     for (int m = 0; m < ndim; m++) total *= global_shape[m];
@@ -1634,6 +1710,14 @@ int pfft_local_block(pfft_plan plan, int layout, int real, int rank, int64_t *sh
     *offset = L.rank_off[rank];
     return PFFT_OK;
     PFFT_GUARD_END
+}
+
+int pfft_layout_axis_order(pfft_plan plan, int layout, int *order)
+{
+    if (!plan || !order) return fail(PFFT_EINVAL, "null argument");
+    if (layout < 0 || layout >= plan->nlayouts) return fail(PFFT_EINVAL, "layout out of range");
+    for (int k = 0; k < plan->ndim; k++) order[k] = plan->layouts[layout].order[k];
+    return PFFT_OK;
 }
 
 int pfft_buffer_bytes(pfft_plan plan, int layout, int real, size_t *bytes)
@@ -1905,7 +1989,7 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
     const uint8_t *dev = (const uint8_t *)b->dev;
     const int sign = direction == 0 ? -1 : 1;
     for (const auto &g : b->groups[direction]) {
-        if (g.kind == KIND_C2C && g.cfg.id >= 0) {
+        if (g.kind == KIND_C2C && g.cfg.id >= 0 && !g.cfg.xside) {
             if (g.ntiles == 0) continue;
             const StageArgs *args = (const StageArgs *)(dev + g.off_args);
             const Tile *tiles = (const Tile *)(dev + g.off_tiles);

@@ -59,20 +59,29 @@ class Plan:
     destroy_input: the transforms may overwrite a complex input and use it
           for intermediates (no workspace for most c2c plans, one buffer
           instead of two for r2c); a real input is never written.
+    transposed_out: the forward output's blocks store their split axes first
+          (the paper's transposed-out alignment; see ``axis_order``).
     """
 
     DEFAULT_PLACEMENT = {"c2c": ("direct", "gather"), "r2c": ("scatter", "gather"), "r2r": ("direct", "gather")}
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], precision: str = "f32", kind: str = "c2c",
                  norm: str = "forward", chain=None, path: str = "fused", device=None,
-                 layouts_only: bool = False, placement=None, destroy_input: bool = False, r2r=None):
+                 layouts_only: bool = False, placement=None, destroy_input: bool = False, r2r=None,
+                 transposed_out: bool = False):
         lib = _lib.load()
         self.shape = tuple(int(x) for x in shape)
         self.grid = tuple(int(x) for x in grid)
         self.precision, self.kind, self.norm, self.path = precision, kind, norm, path
         self.destroy_input = bool(destroy_input)
+        self.transposed_out = bool(transposed_out)
         if placement is None:
-            placement = self.DEFAULT_PLACEMENT[kind]
+            # with the transposed output on grids of two or more directions, the
+            # forward keeps its intermediates (gather) and the backward stores
+            # them in the next stage's layout (scatter): every stage then has
+            # lines that step alike on both sides or a transposing stage kernel
+            placement = (("gather", "scatter") if transposed_out and len(grid) > 1
+                         else self.DEFAULT_PLACEMENT[kind])
         self.placement = (placement, placement) if isinstance(placement, str) else tuple(placement)
         if len(self.placement) != 2 or any(p not in _lib.PLACEMENTS for p in self.placement):
             raise ValueError("placement must be one of %s or a pair of them" % sorted(_lib.PLACEMENTS))
@@ -95,7 +104,8 @@ class Plan:
             ch, nsteps = (ctypes.c_int * max(1, len(flat)))(*flat), len(self.chain)
         flags = (PATHS[path] | (_lib.PFFT_LAYOUTS_ONLY if layouts_only else 0)
                  | (_lib.PLACEMENTS[self.placement[0]] << 3) | (_lib.PLACEMENTS[self.placement[1]] << 5)
-                 | (_lib.PFFT_DESTROY_INPUT if self.destroy_input else 0))
+                 | (_lib.PFFT_DESTROY_INPUT if self.destroy_input else 0)
+                 | (_lib.PFFT_TRANSPOSED_OUT if self.transposed_out else 0))
         prec = 0 if precision == "f32" else 1
         if kind == "r2r":
             kinds = (ctypes.c_int * len(self.shape))(*[R2R_KINDS[k] for k in self.r2r])
@@ -129,6 +139,14 @@ class Plan:
         check(lib.pfft_local_block(self._h, layout, int(real), rank, shp, sta, ctypes.byref(off)),
               "pfft_local_block")
         return tuple(shp), tuple(sta), off.value
+
+    def axis_order(self, layout: int):
+        """Storage order of the layout's blocks: the axis at each position of
+        the block's C-order index."""
+        nd = len(self.shape)
+        out = (ctypes.c_int * nd)()
+        check(_lib.load().pfft_layout_axis_order(self._h, layout, out), "pfft_layout_axis_order")
+        return tuple(out)
 
     def buffer_numel(self, layout: int, real: bool = False) -> int:
         lib = _lib.load()

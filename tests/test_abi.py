@@ -151,6 +151,8 @@ def test_r2r_plan_creation_checks():
     assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, bad, 0, None, 0, 0) == -4
     assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, None, 0, None, 0, 0) == -1
     assert lib.pfft_plan_create(ctypes.byref(h), 3, shp, 2, grd, 0, 2, 0, None, 0, 0) == -4
+    # no transposed output for real-to-real plans
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, ok, 0, None, 0, 1 << 9) == -5
     odd = (ctypes.c_int64 * 3)(16, 5, 8)   # length 5 has no radix plan for the cosine stage
     assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, odd, 2, grd, 0, ok, 0, None, 0, 0) == -5
 

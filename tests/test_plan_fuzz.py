@@ -29,25 +29,27 @@ def plan_cases(draw):
     if draw(st.booleans()) and ngrid == 1:
         # slab moved onto another whole axis
         chain = [(0, draw(st.integers(1, ndim - 1)))]
-    return shape, grid, kind, placement, path, chain
+    transposed = draw(st.booleans())
+    return shape, grid, kind, placement, path, chain, transposed
 
 
 @settings(max_examples=120, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(plan_cases())
 def test_random_plans_validate_and_match_oracle_layouts(case):
-    shape, grid, kind, placement, path, chain = case
+    shape, grid, kind, placement, path, chain, transposed = case
     try:
-        p = Plan(shape, grid, kind=kind, placement=placement, path=path, chain=chain)
+        p = Plan(shape, grid, kind=kind, placement=placement, path=path, chain=chain, transposed_out=transposed)
     except _lib.PfftError as e:
         # only legitimate refusals: r2c needs the last axis whole in layout 0
         assert e.status == -3 and kind == "r2c"
         return
     p.validate()
-    ch = oracle.Chain.paper(shape, grid, kind=kind, steps=chain)
+    ch = oracle.Chain.paper(shape, grid, kind=kind, steps=chain, transposed_out=transposed)
     assert p.num_layouts == len(ch.dirs)
     for li in range(p.num_layouts):
         lay = ch.layout(li)
         offs = lay.offsets()
+        assert p.axis_order(li) == lay.storage
         for r in range(lay.nranks):
             shp, sta, off = p.local_block(li, r)
             assert (shp, sta, off) == (lay.block(r)[0], lay.block(r)[1], offs[r])
