@@ -34,10 +34,12 @@ WORKLOADS = {
     "pencil512_4x4": ((512, 512, 512), (4, 4), "c2c", "f32", None),
     "pencil512_32x16": ((512, 512, 512), (32, 16), "c2c", "f32", None),
     "slab512_thin": ((512, 512, 512), (512,), "c2c", "f32", None),
-    # long lines: 1024^3, and the largest buffers the kernels address (just
+    # long lines: 1024^3, and the largest buffers of 32-bit offsets (just
     # under 2^31 elements, 12 GiB each)
     "c2c1024": ((1024, 1024, 1024), (8, 8), "c2c", "f32", None),
     "max1536": ((1536, 1024, 1024), (8, 8), "c2c", "f32", None),
+    # the paper's largest 3-D size: 2^33 elements, 64 GiB per buffer (64-bit offsets)
+    "c2c2048": ((2048, 2048, 2048), (8, 8), "c2c", "f32", None),
     "pencil256": ((256, 256, 256), (4, 4), "c2c", "f32", None),
     "slab32_f64": ((32, 32, 32), (4,), "c2c", "f64", [(0, 2)]),
     "pencil512_f64": ((512, 512, 512), (8, 8), "c2c", "f64", None),

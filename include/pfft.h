@@ -204,6 +204,8 @@ typedef struct {
                            (the last-level cache), streaming loads, and streaming stores except on
                            stages with the XCD tile order, whose half-row writes are completed in
                            L2 by the neighbouring tile; otherwise 0 */
+    int wide_offsets;   /* 0: 64-bit element offsets only in plans with a buffer of 2^31 elements or
+                           more (those kernels use the default tile shapes); 1: in every stage */
 } pfft_tuning;
 
 int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);

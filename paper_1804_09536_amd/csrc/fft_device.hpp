@@ -372,11 +372,12 @@ __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int
 
 // ---------------------------------------------------------------------------
 // Addressing of one side of a stage for the P positions a thread owns.
-// Offsets are 32-bit (the plan guarantees every buffer has < 2^31 elements).
-template <int P>
+// Offsets are 32-bit (Off = int) where every buffer of the plan has fewer than
+// 2^31 elements, 64-bit (Off = long) in the kernels of larger plans.
+template <int P, typename Off = int>
 struct SideAddr {
-    int off[P];     // element offset of position m in line 0 of the tile
-    int stride[P];  // distance between consecutive lines of the tile
+    Off off[P];     // element offset of position m in line 0 of the tile
+    Off stride[P];  // distance between consecutive lines of the tile
 
     __device__ __forceinline__ void init(const Side &sd, const Tile &t, int s, int jt, int TPL, int N, bool contig)
     {
@@ -392,8 +393,8 @@ struct SideAddr {
                 const int c = (unsigned)j / (unsigned)un;
                 const int loc = j - c * un;
                 const long base = (long)(rank + c * sd.R) * sd.ublock;
-                off[m] = (int)(base + (O * un + loc) * E + I);
-                stride[m] = contig ? (int)(un * E) : 1;
+                off[m] = (Off)(base + (O * un + loc) * E + I);
+                stride[m] = contig ? (Off)(un * E) : (Off)1;
             }
             return;
         }
@@ -415,8 +416,8 @@ struct SideAddr {
         }
 #pragma unroll
         for (int m = 0; m < P; m++) {
-            off[m] = (int)(base[m] + (O * na[m] + pc[m].y) * E + I);
-            stride[m] = contig ? (int)(na[m] * E) : 1;
+            off[m] = (Off)(base[m] + (O * na[m] + pc[m].y) * E + I);
+            stride[m] = contig ? (Off)(na[m] * E) : (Off)1;
         }
     }
 };

@@ -60,7 +60,8 @@ struct C2CDefault {
 // with another storage order: lines adjacent on one side, each line
 // contiguous on the other); loads keep the kernel's mode, stores go point by
 // point to line w at O + w (strided kernels) or I + w (contiguous kernels).
-template <typename T, int N, bool CONTIG, int SIGN, class S, bool STREAM = true, bool XS = false>
+template <typename T, int N, bool CONTIG, int SIGN, class S, bool STREAM = true, bool XS = false,
+          typename Off = int>
 struct C2CWorker {
     using T2 = typename V2<T>::type;
     using T4 = typename V2<T>::quad;
@@ -120,8 +121,8 @@ struct C2CWorker {
     }
 
     // Element offset of line l at position m.
-    __device__ __forceinline__ static int at(const SideAddr<P> &sa, const int (&lo)[NL], const int (&wl_)[NL], int l,
-                                             int m)
+    __device__ __forceinline__ static Off at(const SideAddr<P, Off> &sa, const int (&lo)[NL], const int (&wl_)[NL],
+                                             int l, int m)
     {
         if constexpr (CONTIG)
             return sa.off[m] + wl_[l] * sa.stride[m];
@@ -132,13 +133,13 @@ struct C2CWorker {
     // Compute both sides' addresses of tile `ti` and issue its loads.  A full
     // tile whose addresses are even on both sides (Tile flag bit 0) takes the
     // unpredicated path; others are predicated line by line.
-    __device__ __forceinline__ void load(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], SideAddr<P> &dst,
+    __device__ __forceinline__ void load(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], SideAddr<P, Off> &dst,
                                          int &count) const
     {
         count = t.count;
         const bool fast = (t.count == W) && (VEC == 1 || (t.flags & 1));
         if (!fast) count = -count;  // sign marks the predicated path for process()
-        SideAddr<P> src;
+        SideAddr<P, Off> src;
         src.init(a.side[0], t, 0, jt, TPL, N, CONTIG);
         dst.init(a.side[1], t, 1, jt, TPL, N, XS ? !CONTIG : CONTIG);
         const T2 *__restrict__ in = (const T2 *)a.src;
@@ -181,8 +182,8 @@ struct C2CWorker {
     }
 
     // Transform the registers of one tile (LDS-staged passes), scale, store.
-    __device__ __forceinline__ void process(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], const SideAddr<P> &dst,
-                                            int count, T2 *lds, const T2 *tw) const
+    __device__ __forceinline__ void process(const StageArgs &a, const Tile &t, T2 (&v)[NL][P],
+                                            const SideAddr<P, Off> &dst, int count, T2 *lds, const T2 *tw) const
     {
         if constexpr (fft_npasses(N) > 1) __syncthreads();  // the previous tile's last LDS reads are done
         fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, tw);
@@ -256,11 +257,12 @@ struct C2CWorker {
 };
 
 // Occupancy target of a tile shape: two workgroups per CU when their LDS fits
-// (which caps VGPRs at 128 for 512-thread workgroups).
-template <class S>
+// (which caps VGPRs at 128 for 512-thread workgroups); the 64-bit-offset
+// kernels of the largest plans leave the compiler their extra registers.
+template <class S, typename Off = int>
 constexpr int c2c_waves_per_eu()
 {
-    return (S::NT == 512 && S::H > 1) ? 4 : 1;
+    return (S::NT == 512 && S::H > 1 && sizeof(Off) == 4) ? 4 : 1;
 }
 
 // Twiddle table of the stage staged in LDS once per workgroup (the passes
@@ -289,11 +291,11 @@ struct TwiddleStage {
 // `tiles` is a.tiles passed as a restrict-qualified argument: tile records
 // are then known to be unchanged by the kernel's stores and can be read
 // through the scalar cache.
-template <typename T, int N, bool CONTIG, int SIGN, class S, bool XS = false>
-__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S>()))) void k_c2c(
+template <typename T, int N, bool CONTIG, int SIGN, class S, bool XS = false, typename Off = int>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves_per_eu<S, Off>()))) void k_c2c(
     StageArgs a, const Tile *__restrict__ tiles)
 {
-    using Wk = C2CWorker<T, N, CONTIG, SIGN, S, true, XS>;
+    using Wk = C2CWorker<T, N, CONTIG, SIGN, S, true, XS, Off>;
     using T2 = typename Wk::T2;
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     wk.init_geometry();
     const long G = gridDim.x, nt = a.ntiles;
     T2 v[NL][P];
-    SideAddr<P> d;
+    SideAddr<P, Off> d;
     int c;
     // SF_XCD_ORDER with one tile per workgroup: workgroup b runs on XCD
     // b % 8, which takes the contiguous range x*q + min(x, r) + [0, q + (x < r))

@@ -74,6 +74,19 @@ static hipError_t c2c_launch_xs(const KernelConfig &c, const StageArgs &a, hipSt
     return hipGetLastError();
 }
 
+// The stage of plans with buffers of 2^31 elements or more: 64-bit offsets,
+// the same default tile shape, one tile per workgroup.
+template <typename T, int N, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_wide(const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    using S = typename C2CXsShape<T, N, CONTIG>::type;
+    (void)c;
+    long g = a.ntiles < 1 ? 1 : a.ntiles;
+    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S, false, long>), dim3((unsigned)g), dim3(S::NT), 0, s, a,
+                       a.tiles);
+    return hipGetLastError();
+}
+
 template <typename T, int N, bool CONTIG, int SIGN, int V>
 static hipError_t c2c_launch_multi_v(const KernelConfig &c, const StageArgs *args, const Tile *tiles, long nt,
                                      hipStream_t s)
@@ -120,6 +133,7 @@ template <typename T, int N, bool CONTIG, int SIGN>
 static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
     if (c.xside) return c2c_launch_xs<T, N, CONTIG, SIGN>(c, a, s);
+    if (c.wide) return c2c_launch_wide<T, N, CONTIG, SIGN>(c, a, s);
     switch (c.id) {
     case 1:
         if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
@@ -142,11 +156,12 @@ template <typename T, int N, bool CONTIG>
 static void c2c_cfg_mode(int variant, KernelConfig *c)
 {
     int W, NT, id;
-    if (variant == 6) {  // the XS stage's shape
+    if (variant == 6 || variant == 7) {  // the shape of the XS stage (6) and of the 64-bit-offset stage (7)
         c->W = C2CXsShape<T, N, CONTIG>::type::W;
         c->threads = C2CXsShape<T, N, CONTIG>::type::NT;
         c->id = C2CXsShape<T, N, CONTIG>::V;
-        c->xside = 1;
+        c->xside = variant == 6;
+        c->wide = variant == 7;
         return;
     }
     if (variant == 1 && C2CVariant<T, N, CONTIG, 1>::exists) {

@@ -13,7 +13,7 @@ constexpr int kCopyUnroll = 8;
 
 // One workgroup per tile of lines; TPL threads per line slot (a power of two
 // <= 64), positions j = jt + u*TPL in chunks of kCopyUnroll per thread.
-template <typename E>
+template <typename E, typename Off>
 __global__ __launch_bounds__(kCopyThreads) void k_copy(StageArgs a, int TPL)
 {
     const Tile &t = a.tiles[blockIdx.x];
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_copy(StageArgs a, int TPL)
     const E *__restrict__ in = (const E *)a.src;
     E *__restrict__ out = (E *)a.dst;
     for (int j0 = 0; j0 < N; j0 += TPL * kCopyUnroll) {
-        SideAddr<kCopyUnroll> s, d;
+        SideAddr<kCopyUnroll, Off> s, d;
         // lines step in O (contiguous lines) unless the tile says I on that side
         s.init(a.side[0], t, 0, j0 + jt, TPL, N, !(t.flags & 4));
         d.init(a.side[1], t, 1, j0 + jt, TPL, N, !(t.flags & 8));
@@ -73,10 +73,15 @@ int copy_config(int N, KernelConfig *cfg)
 hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.ntiles), block(kCopyThreads);
-    switch (esize) {
-    case 4: hipLaunchKernelGGL((k_copy<float>), grid, block, 0, s, a, cfg.id); break;
-    case 8: hipLaunchKernelGGL((k_copy<float2>), grid, block, 0, s, a, cfg.id); break;
-    case 16: hipLaunchKernelGGL((k_copy<double2>), grid, block, 0, s, a, cfg.id); break;
+    // 64-bit offsets in plans with buffers of 2^31 elements or more
+    const long key = (long)esize * (cfg.wide ? -1 : 1);
+    switch (key) {
+    case 4: hipLaunchKernelGGL((k_copy<float, int>), grid, block, 0, s, a, cfg.id); break;
+    case 8: hipLaunchKernelGGL((k_copy<float2, int>), grid, block, 0, s, a, cfg.id); break;
+    case 16: hipLaunchKernelGGL((k_copy<double2, int>), grid, block, 0, s, a, cfg.id); break;
+    case -4: hipLaunchKernelGGL((k_copy<float, long>), grid, block, 0, s, a, cfg.id); break;
+    case -8: hipLaunchKernelGGL((k_copy<float2, long>), grid, block, 0, s, a, cfg.id); break;
+    case -16: hipLaunchKernelGGL((k_copy<double2, long>), grid, block, 0, s, a, cfg.id); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

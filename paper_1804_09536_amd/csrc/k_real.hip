@@ -24,7 +24,8 @@ struct RealLds {
 };
 
 // S: the launch shape of the M-point transform (a contiguous-mode C2CCfg).
-template <typename T, int NR, int KIND, class S>
+// Off: element offsets (long in the plans with buffers of 2^31 elements or more).
+template <typename T, int NR, int KIND, class S, typename Off = int>
 __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restrict__ tiles)
 {
     using T2 = typename V2<T>::type;
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
 
     if constexpr (KIND == KIND_R2C) {
         // real side: pairs (2n, 2n+1) of real positions, n = jt + m*TPL
-        SideAddr<P> rs;
+        SideAddr<P, Off> rs;
         rs.init(a.side[0], t, 0, 2 * jt, 2 * TPL, NR, true);
         const T *__restrict__ in = (const T *)a.src;
         if (count == W) {
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
 #pragma unroll
             for (int m = 0; m < P; m++) lds[RL::idx(wl[l], jt + m * TPL)] = v[l][m];
         __syncthreads();
-        SideAddr<P> cs;
+        SideAddr<P, Off> cs;
         cs.init(a.side[1], t, 1, jt, TPL, M + 1, true);
         T2 *__restrict__ out = (T2 *)a.dst;
         const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
     } else {
         // complex side: bins k = jt + m*TPL and bin M, through LDS
         const T2 *__restrict__ in = (const T2 *)a.src;
-        SideAddr<P> cs;
+        SideAddr<P, Off> cs;
         cs.init(a.side[0], t, 0, jt, TPL, M + 1, true);
         const bool half = (a.flags & SF_HALVE_INTERIOR) != 0;
         // all loads first (a full tile without predicates), then the LDS
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
             }
         __syncthreads();
         fft_passes<T2, M, W, true, 1, NL, 1, 0>(v, wl, jt, lds, tw);
-        SideAddr<P> rs;
+        SideAddr<P, Off> rs;
         rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
         T *__restrict__ out = (T *)a.dst;
         if (count == W && a.side[1].R == 0) {
@@ -239,7 +240,9 @@ struct RealShape {
 template <typename T>
 static int real_config_t(int NR, int variant, KernelConfig *cfg)
 {
-    const int v = variant == 1 ? 1 : 0;
+    // variant 7: the 64-bit-offset kernel with the default shape (1)
+    const int v = (variant == 1 || variant == 7) ? 1 : 0;
+    cfg->wide = variant == 7;
     switch (NR) {
 #define PFFT_CASE(n)                                                                              \
     case n:                                                                                       \
@@ -254,24 +257,26 @@ static int real_config_t(int NR, int variant, KernelConfig *cfg)
     }
 }
 
-template <typename T, int NR, int V>
+template <typename T, int NR, int V, typename Off = int>
 static hipError_t real_launch_v(int kind, const StageArgs &a, hipStream_t s)
 {
     using S = typename RealShape<T, NR>::template type<V>;
     dim3 grid((unsigned)a.ntiles);
     if (kind == KIND_R2C)
-        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, a, a.tiles);
+        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
     else
-        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, a, a.tiles);
+        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t real_launch_t(int NR, int kind, int variant, const StageArgs &a, hipStream_t s)
+static hipError_t real_launch_t(int NR, int kind, int variant, int wide, const StageArgs &a, hipStream_t s)
 {
     switch (NR) {
-#define PFFT_CASE(n) \
-    case n: return variant == 1 ? real_launch_v<T, n, 1>(kind, a, s) : real_launch_v<T, n, 0>(kind, a, s);
+#define PFFT_CASE(n)                                                                      \
+    case n:                                                                               \
+        return wide ? real_launch_v<T, n, 1, long>(kind, a, s)                            \
+                    : (variant == 1 ? real_launch_v<T, n, 1>(kind, a, s) : real_launch_v<T, n, 0>(kind, a, s));
         PFFT_FOR_EACH_NR(PFFT_CASE)
 #undef PFFT_CASE
     default:
@@ -287,7 +292,8 @@ int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg)
 
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s)
 {
-    return prec == 0 ? real_launch_t<float>(N, kind, cfg.id, a, s) : real_launch_t<double>(N, kind, cfg.id, a, s);
+    return prec == 0 ? real_launch_t<float>(N, kind, cfg.id, cfg.wide, a, s)
+                     : real_launch_t<double>(N, kind, cfg.id, cfg.wide, a, s);
 }
 
 }  // namespace pfft

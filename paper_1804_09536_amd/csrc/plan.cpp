@@ -402,7 +402,7 @@ struct LineRec {
 // Enumerate every line of a stage along `axis` (source layout A, destination
 // layout B) and group them into tiles of at most W lines that are adjacent in
 // both layouts.
-static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
+static bool build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
 {
     const Layout &A = p->layouts[ln.src];
     const Layout &B = p->layouts[ln.dst];
@@ -452,6 +452,7 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
             rec.O[s] = O;
             rec.E[s] = E;
             rec.I[s] = I;
+            if (O > INT32_MAX || E > INT32_MAX) return false;  // tile records hold 32-bit indices
         }
         lines.push_back(rec);
     }
@@ -634,6 +635,7 @@ static void build_tiles(pfft_plan_s *p, Launch &ln, int W, bool wrap)
               dst_bytes > 256.0 * 1048576.0)
                  ? 1
                  : 0;
+    return true;
 }
 
 static int add_layout(pfft_plan_s *p, const int64_t *shape, int ngrid, const int64_t *grid, const int *dirs,
@@ -653,9 +655,14 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         const bool last_d = p->layouts[ln.dst].pos_of[ln.axis] == p->ndim - 1;
         ln.mixed_sides = last_s != last_d;
     }
-    if (p->layouts[ln.src].total() >= ((int64_t)1 << 31) || p->layouts[ln.dst].total() >= ((int64_t)1 << 31))
-        return fail(PFFT_EUNSUPPORTED, "buffers of 2^31 or more elements are not supported");
     const pfft_tuning &tu = p->tuning;
+    // 64-bit element offsets where a buffer has 2^31 elements or more (or
+    // where the tuning asks for them): the kernels' own variants with the
+    // default tile shapes
+    const bool wide = p->layouts[ln.src].total() >= ((int64_t)1 << 31) ||
+                      p->layouts[ln.dst].total() >= ((int64_t)1 << 31) || tu.wide_offsets == 1;
+    if (wide && ln.kind == KIND_R2R)
+        return fail(PFFT_EUNSUPPORTED, "real-to-real plans with buffers of 2^31 or more elements are not supported");
     int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
                       ? (ln.contig ? tu.tile_contig : tu.tile_strided)
                       : 0;
@@ -666,14 +673,19 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     if (ln.mixed_sides && ln.kind != KIND_COPY) {
         // lines contiguous on one side and adjacent on the other: the stage
         // kernel in the source's mode with the destination stepped the other
-        // way (or, for lengths without a register plan, the LDS kernel, which
-        // loads and stores each side in its own order)
+        // way (or, for lengths without a register plan and in plans with
+        // 64-bit offsets, the LDS kernel, which loads and stores each side in
+        // its own order)
         ln.contig = p->layouts[ln.src].pos_of[ln.axis] == p->ndim - 1 ? 1 : 0;
-        rc = ln.kind == KIND_C2C ? kernel_config(ln.kind, prec, ln.N, ln.contig, 6, &ln.cfg) : -1;
+        if (ln.kind != KIND_C2C) rc = -1;
+        else if (wide) rc = mixed_config(prec, ln.N, ln.kind, &ln.cfg);
+        else rc = kernel_config(ln.kind, prec, ln.N, ln.contig, 6, &ln.cfg);
     } else {
-        rc = kernel_config(ln.kind, prec, ln.N, ln.contig, variant, &ln.cfg);
+        rc = kernel_config(ln.kind, prec, ln.N, ln.contig, wide && ln.kind != KIND_COPY ? 7 : variant, &ln.cfg);
+        if (ln.kind == KIND_COPY) ln.cfg.wide = wide ? 1 : 0;
     }
-    if (ln.kind == KIND_C2C) ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
+    if (ln.kind == KIND_C2C && !ln.cfg.wide && !ln.cfg.xside)
+        ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0) {
         if (ln.kind == KIND_R2R)
             return fail(PFFT_EUNSUPPORTED, "no real-to-real kernel for length " + std::to_string(ln.N) +
@@ -708,7 +720,8 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         ln.off_tw2 = twiddle_table(p, 4 * ln.N);  // its first N entries are e^{-i pi k / 2N}
     }
     // runs shorter than a tile are chained only for the Stockham stage kernels
-    build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig && !ln.mixed_sides);
+    if (!build_tiles(p, ln, ln.cfg.W, ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.contig && !ln.mixed_sides && !wide))
+        return fail(PFFT_EUNSUPPORTED, "a block's outer or inner index range exceeds 2^31 elements");
     if (ln.kind == KIND_C2C && !ln.contig && tu.xcd_order != 0) ln.xcd = tu.xcd_order == 1 ? 1 : 0;
     // Streaming accesses on strided rows where source and destination
     // together exceed the 256 MB last-level cache (512^3 pencil stages -4..-7 %
@@ -973,6 +986,7 @@ static pfft_tuning default_tuning()
     t.resident_strided = 0;
     t.xcd_order = 0;
     t.stream_strided = 4;
+    t.wide_offsets = 0;
     return t;
 }
 
@@ -1607,7 +1621,8 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
     if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
     if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 5 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1 ||
-        t->xcd_order < 0 || t->xcd_order > 2 || t->stream_strided < 0 || t->stream_strided > 4)
+        t->xcd_order < 0 || t->xcd_order > 2 || t->stream_strided < 0 || t->stream_strided > 4 || t->wide_offsets < 0 ||
+        t->wide_offsets > 1)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again
     plan->tuning = *t;

@@ -171,10 +171,27 @@ def test_r2r_layouts_match_oracle_and_validate():
     p.validate()
 
 
-def test_buffers_of_2_31_elements_are_refused():
-    # kernels address buffers with 32-bit element offsets: 2^31 elements is one too many
-    assert _create((2048, 1024, 1024), (8, 8)) == -5
-    assert _create((1536, 1024, 1024), (8, 8), flags=4) == 0
+def test_buffers_of_2_31_elements_take_wide_offsets():
+    # from 2^31 elements on, plans use the kernels' 64-bit-offset variants;
+    # real-to-real plans have none and are refused
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan((2048, 1024, 1024), (8, 8), device="cpu")
+    assert p.buffer_numel(0) == 2 ** 31
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    shp = (ctypes.c_int64 * 3)(2048, 1024, 1024)
+    grd = (ctypes.c_int * 2)(8, 8)
+    kinds = (ctypes.c_int * 3)(0, 0, 0)
+    assert lib.pfft_plan_create_r2r(ctypes.byref(h), 3, shp, 2, grd, 0, kinds, 0, None, 0, 0) == -5
+
+
+@pytest.mark.parametrize("shape,grid,kind", [((16, 24, 32), (2, 3), "c2c"), ((12, 16, 20), (4,), "r2c"),
+                                             ((8, 12, 6, 10), (2, 2, 3), "c2c"), ((16, 24, 32), (2, 3), "c2c_tr")])
+def test_forced_wide_offsets_validate(shape, grid, kind):
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan(shape, grid, kind=kind[:3], transposed_out=kind.endswith("_tr"), device="cpu")
+    p.set_tuning(wide_offsets=1)
+    p.validate()
 
 
 def test_weighted_energy_argument_checks():

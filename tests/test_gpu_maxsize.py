@@ -1,4 +1,4 @@
-"""The largest buffers the kernels address (just under 2^31 elements:
+"""The largest buffers of the 32-bit-offset kernels (just under 2^31 elements:
 1536x1024x1024 complex64, 12 GiB per buffer) on the metric's 8x8 grid, checked
 against closed forms over every output element: a separable plane wave
 e^{2 pi i m.j / N} transforms to a unit delta at k = m (Eq. multifft with the
