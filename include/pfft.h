@@ -132,7 +132,11 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_MAX_DIMS 8
 
 /*
- * Create a plan (host memory only).
+ * Create a plan (host memory only): the setup phase of Sec. 3.2.2 (index
+ * tables built once and reused, the role of the subarray datatypes of
+ * Alg. SubArray), the decomposition of Sec. 3.1 (Eq. decompose) over the
+ * Cartesian grid of Sec. 3.3, and the chain of alignments of Eqs.
+ * pencil0-pencil2 / 4d_fft0-4d_fft3.
  *   ndim, global_shape: the global array, 1 <= ndim <= 8, every extent >= 1.
  *     For PFFT_R2C, global_shape is the real array's shape.
  *   grid_ndim, grid_dims: the virtual process grid, 1 <= grid_ndim < ndim,
@@ -214,7 +218,9 @@ int pfft_plan_get_tuning(pfft_plan plan, pfft_tuning *tuning);
 /* Destroy a plan (host memory).  The caller frees the device state. */
 int pfft_plan_destroy(pfft_plan plan);
 
-/* Number of layouts in the chain (g+1 for the paper's rule). */
+/* Number of layouts in the chain: g+1 for the paper's rule on a g-dimensional
+   grid (Secs. 3.2.1, 3.4, 3.5: one alignment per redistribution plus the
+   input alignment). */
 int pfft_num_layouts(pfft_plan plan, int *n);
 
 /*
@@ -232,7 +238,8 @@ int pfft_local_block(pfft_plan plan, int layout, int real, int rank, int64_t *sh
    PFFT_TRANSPOSED_OUT plan). */
 int pfft_layout_axis_order(pfft_plan plan, int layout, int *order);
 
-/* Bytes of a layout's buffer (real = as above). */
+/* Bytes of a layout's buffer (real = as above): the sum over the ranks of
+   the local block sizes of Eq. decompose (Sec. 3.1), times the element size. */
 int pfft_buffer_bytes(pfft_plan plan, int layout, int real, size_t *bytes);
 
 /* Bytes of device state (tile and index tables, twiddles) the plan needs. */
@@ -260,13 +267,18 @@ int pfft_redistribute(pfft_plan plan, int layout_from, int layout_to, const void
                       hipStream_t stream);
 
 /*
- * Forward transform: `in` in layout 0 (real for R2C), `out` in the last
- * layout (half spectrum for R2C).  `work`: pfft_workspace_bytes bytes.
- * `in` is left unchanged unless the plan has PFFT_DESTROY_INPUT.
+ * Forward transform (Eq. fftn_forward through the chain's redistributions,
+ * e.g. Eqs. pencil0-pencil2; Eq. multifft with the norm's factors): `in` in
+ * layout 0 (real for R2C), `out` in the last layout (half spectrum for R2C).
+ * `work`: pfft_workspace_bytes bytes.  `in` is left unchanged unless the
+ * plan has PFFT_DESTROY_INPUT.  Errors: PFFT_EINVAL (null, misaligned or
+ * overlapping buffers), PFFT_EWORKSPACE (device state not bound),
+ * PFFT_EUNSUPPORTED (layouts-only plan), PFFT_EHIP (a launch failed).
  */
 int pfft_forward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
 
-/* Backward transform: `in` in the last layout, `out` in layout 0. */
+/* Backward transform (Eq. fftn_backward, the mirror chain, sign +1):
+   `in` in the last layout, `out` in layout 0.  Errors as pfft_forward. */
 int pfft_backward(pfft_plan plan, const void *in, void *out, void *work, hipStream_t stream);
 
 /*
@@ -291,8 +303,11 @@ int pfft_adjoint_backward(pfft_plan plan, const void *in, void *out, void *work,
  * HIP graph.  The batch copies what it needs from its plans at creation
  * (member plans may be changed or destroyed afterwards).
  *
- * Buffers: one input, one output and one workspace buffer for the whole
- * batch, each holding every member's region at the offsets
+ * Buffers are bound once (pfft_batch_bind), not passed to every execution:
+ * the grouped launches read every member's kernel arguments from device
+ * memory, so binding writes them once and an execution (or a captured graph
+ * of it) only launches.  One input, one output and one workspace buffer for
+ * the whole batch, each holding every member's region at the offsets
  * pfft_batch_member_offsets returns (256-byte aligned); a member's input
  * region is its layout 0, its output region its last layout.  Direction 0
  * runs every member's forward transform (input -> output), direction 1 every
