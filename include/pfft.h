@@ -210,6 +210,14 @@ typedef struct {
                            L2 by the neighbouring tile; otherwise 0 */
     int wide_offsets;   /* 0: 64-bit element offsets only in plans with a buffer of 2^31 elements or
                            more (those kernels use the default tile shapes); 1: in every stage */
+    int radix_alt;      /* complex stages of 32-32768 points (powers of two from 32, 3*2^a from 48):
+                           bit 0 contiguous stages, bit 1 strided stages take the alternative radix
+                           plan (16 points per thread instead of 8, or 8 instead of 16 from 1024
+                           points on; 8 instead of 4 times 3, or 4 instead of 8, for 3*2^a), with the
+                           mode's default tile width; 0 (the default) none.  Results change only by
+                           rounding.  Stages with 64-bit offsets or differently stepping sides, and
+                           other lengths, keep their kernels; such stages leave the multi-transform
+                           kernel of batches. */
 } pfft_tuning;
 
 int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);

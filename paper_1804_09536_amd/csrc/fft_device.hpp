@@ -236,31 +236,44 @@ __host__ __device__ constexpr int fft_p2(int N)
     return N2 <= 8 ? N2 : (N2 <= 256 ? 4 : 8);
 }
 
-__host__ __device__ constexpr int fft_points(int N) { return is_pow2(N) ? fft_p2(N) : 3 * fft_p2(N); }
+// The alternative radix plan of a length (a result-neutral tuning choice):
+// the other power-of-two part, 16 instead of 8 points per thread (or 8
+// instead of 16 from 1024 on) for powers of two from 32, 8 instead of 4 (or
+// 4 instead of 8) for 3 * 2^a from 48; other lengths have none.
+__host__ __device__ constexpr int fft_p2_alt(int N)
+{
+    if (is_pow2(N)) return N < 32 ? fft_p2(N) : (fft_p2(N) == 8 ? 16 : 8);
+    return N / 3 <= 8 ? fft_p2(N) : (fft_p2(N) == 4 ? 8 : 4);
+}
+__host__ __device__ constexpr int fft_p2a(int N, int ALT) { return ALT ? fft_p2_alt(N) : fft_p2(N); }
 
-__host__ __device__ constexpr int fft_npasses(int N)
+__host__ __device__ constexpr int fft_points_a(int N, int ALT) { return is_pow2(N) ? fft_p2a(N, ALT) : 3 * fft_p2a(N, ALT); }
+__host__ __device__ constexpr int fft_points(int N) { return fft_points_a(N, 0); }
+
+__host__ __device__ constexpr int fft_npasses_a(int N, int ALT)
 {
     int n = 0, rem = pow2_part(N);
-    const int P = fft_p2(N);
+    const int P = fft_p2a(N, ALT);
     while (rem > 1) {
         rem = rem >= P ? rem / P : 1;
         n++;
     }
     return is_pow2(N) ? n : n + 1;
 }
+__host__ __device__ constexpr int fft_npasses(int N) { return fft_npasses_a(N, 0); }
 
-__host__ __device__ constexpr int fft_radix(int N, int pass)
+__host__ __device__ constexpr int fft_radix_a(int N, int ALT, int pass)
 {
-    if (!is_pow2(N) && pass == fft_npasses(N) - 1) return 3;
-    int P = fft_p2(N), rem = pow2_part(N);
+    if (!is_pow2(N) && pass == fft_npasses_a(N, ALT) - 1) return 3;
+    int P = fft_p2a(N, ALT), rem = pow2_part(N);
     for (int i = 0; i < pass; i++) rem = rem >= P ? rem / P : 1;
     return rem >= P ? P : rem;
 }
 
-__host__ __device__ constexpr int fft_span(int N, int pass)  // L = product of radices before `pass`
+__host__ __device__ constexpr int fft_span_a(int N, int ALT, int pass)  // L = product of radices before `pass`
 {
     int L = 1;
-    for (int i = 0; i < pass; i++) L *= fft_radix(N, i);
+    for (int i = 0; i < pass; i++) L *= fft_radix_a(N, ALT, i);
     return L;
 }
 
@@ -334,14 +347,15 @@ struct LdsTile {
 // transform's output point jt + m*TPL.  The LDS holds WL lines: with H > 1
 // portions, slots [h*NL/H, (h+1)*NL/H) (lines [h*WL, (h+1)*WL)) exchange in
 // turn, so a tile of H*WL lines needs the LDS of WL lines.
-template <typename T2, int N, int WL, bool CONTIG, int SIGN, int NL, int H, int PASS>
-__device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int (&wl)[NL], int jt, T2 *lds,
+// ALT selects the alternative radix plan (fft_p2_alt).
+template <typename T2, int N, int WL, bool CONTIG, int SIGN, int NL, int H, int PASS, int ALT = 0>
+__device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points_a(N, ALT)], const int (&wl)[NL], int jt, T2 *lds,
                                            const T2 *__restrict__ tw)
 {
-    constexpr int P = fft_points(N);
-    constexpr int NP = fft_npasses(N);
-    constexpr int R = fft_radix(N, PASS);
-    constexpr int L = fft_span(N, PASS);
+    constexpr int P = fft_points_a(N, ALT);
+    constexpr int NP = fft_npasses_a(N, ALT);
+    constexpr int R = fft_radix_a(N, ALT, PASS);
+    constexpr int L = fft_span_a(N, ALT, PASS);
     constexpr int TPL = N / P;
     constexpr int NLH = NL / H;
     static_assert(NL % H == 0, "portions must split the line slots evenly");
@@ -366,7 +380,7 @@ __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points(N)], const int
 #pragma unroll
                 for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l] - h * WL, jt + m * TPL)];
         }
-        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1>(v, wl, jt, lds, tw);
+        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1, ALT>(v, wl, jt, lds, tw);
     }
 }
 

@@ -22,9 +22,10 @@
 
 namespace pfft {
 
-template <typename T, int N, bool CONTIG, int W_, int NL_, int H_ = 1>
+template <typename T, int N, bool CONTIG, int W_, int NL_, int H_ = 1, int ALT_ = 0>
 struct C2CCfg {
-    static constexpr int P = fft_points(N);
+    static constexpr int ALT = ALT_;                                 // alternative radix plan
+    static constexpr int P = fft_points_a(N, ALT_);
     static constexpr int TPL = N / P;                                // threads per line slot
     static constexpr int VEC = (!CONTIG && sizeof(T) == 4) ? 2 : 1;  // lines per access
     static constexpr int W = W_;                                     // lines per tile
@@ -67,7 +68,7 @@ struct C2CWorker {
     using T4 = typename V2<T>::quad;
     static constexpr int P = S::P, TPL = S::TPL, VEC = S::VEC, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
     using LT = LdsTile<T2, N, S::WL, CONTIG>;
-    static constexpr int LDS_SIZE = (fft_npasses(N) > 1) ? LT::SIZE : 1;
+    static constexpr int LDS_SIZE = (fft_npasses_a(N, S::ALT) > 1) ? LT::SIZE : 1;
 
     int jt, slot;
     int wl[NL];
@@ -185,8 +186,8 @@ struct C2CWorker {
     __device__ __forceinline__ void process(const StageArgs &a, const Tile &t, T2 (&v)[NL][P],
                                             const SideAddr<P, Off> &dst, int count, T2 *lds, const T2 *tw) const
     {
-        if constexpr (fft_npasses(N) > 1) __syncthreads();  // the previous tile's last LDS reads are done
-        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0>(v, wl, jt, lds, tw);
+        if constexpr (fft_npasses_a(N, S::ALT) > 1) __syncthreads();  // the previous tile's last LDS reads are done
+        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0, S::ALT>(v, wl, jt, lds, tw);
         const T scale = (T)a.scale;
         if (scale != (T)1) {
 #pragma unroll

@@ -56,6 +56,32 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
     return hipGetLastError();
 }
 
+// The alternative radix plan with the measured default tile shape of the
+// mode (lines per tile and LDS portions of that shape, lines per thread
+// chosen for at most 512 threads).
+template <typename T, int N, bool CONTIG>
+struct C2CAlt {
+    static constexpr int VD = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
+    using Base = typename C2CVariant<T, N, CONTIG, C2CVariant<T, N, CONTIG, VD>::exists ? VD : 0>::type;
+    static constexpr int W = Base::W, H = Base::H, VEC = Base::VEC;
+    static constexpr int TPLA = N / fft_points_a(N, 1);
+    static constexpr int nl_for(int nl) { return (TPLA * W / nl > 512 && nl < W) ? nl_for(nl * 2) : nl; }
+    static constexpr int NL = nl_for(H * VEC);
+    static constexpr bool exists =
+        N >= 32 && fft_p2_alt(N) != fft_p2(N) && W % NL == 0 && TPLA * (W / NL) <= 512 && TPLA >= 1;
+    using type = C2CCfg<T, N, CONTIG, W, exists ? NL : Base::NL, H, exists ? 1 : 0>;
+};
+
+template <typename T, int N, bool CONTIG, int SIGN>
+static hipError_t c2c_launch_alt(const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    using S = typename C2CAlt<T, N, CONTIG>::type;
+    (void)c;
+    long g = a.ntiles < 1 ? 1 : a.ntiles;
+    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
 // The stage whose destination lines step the other way (XS), with the
 // measured default tile shape of the kernel's mode.
 template <typename T, int N, bool CONTIG>
@@ -134,6 +160,9 @@ static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStr
 {
     if (c.xside) return c2c_launch_xs<T, N, CONTIG, SIGN>(c, a, s);
     if (c.wide) return c2c_launch_wide<T, N, CONTIG, SIGN>(c, a, s);
+    if (c.alt) {
+        if constexpr (C2CAlt<T, N, CONTIG>::exists) return c2c_launch_alt<T, N, CONTIG, SIGN>(c, a, s);
+    }
     switch (c.id) {
     case 1:
         if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
@@ -156,6 +185,16 @@ template <typename T, int N, bool CONTIG>
 static void c2c_cfg_mode(int variant, KernelConfig *c)
 {
     int W, NT, id;
+    if (variant == 8) {  // the alternative radix plan, where the length has one
+        if constexpr (C2CAlt<T, N, CONTIG>::exists) {
+            c->W = C2CAlt<T, N, CONTIG>::type::W;
+            c->threads = C2CAlt<T, N, CONTIG>::type::NT;
+            c->id = 8;
+            c->alt = 1;
+            return;
+        }
+        variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
+    }
     if (variant == 6 || variant == 7) {  // the shape of the XS stage (6) and of the 64-bit-offset stage (7)
         c->W = C2CXsShape<T, N, CONTIG>::type::W;
         c->threads = C2CXsShape<T, N, CONTIG>::type::NT;

@@ -19,6 +19,7 @@ struct KernelConfig {
     int resident = 0;  // 1: grid = resident workgroups looping over tiles; 0: one tile per workgroup
     int xside = 0;     // complex stage whose destination lines step the other way (variant 6)
     int wide = 0;      // 64-bit element offsets (buffers of 2^31 elements or more; variant 7)
+    int alt = 0;       // the alternative radix plan (variant 8)
 };
 
 // Fills cfg for a stage kernel (kind: StageKind; prec: 0 = f32, 1 = f64;

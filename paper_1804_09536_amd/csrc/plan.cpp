@@ -681,10 +681,13 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         else if (wide) rc = mixed_config(prec, ln.N, ln.kind, &ln.cfg);
         else rc = kernel_config(ln.kind, prec, ln.N, ln.contig, 6, &ln.cfg);
     } else {
+        // the alternative radix plan where the tuning asks for it (complex
+        // stages of lengths that have one; others keep their variant)
+        if (ln.kind == KIND_C2C && !wide && (tu.radix_alt & (ln.contig ? 1 : 2)) != 0) variant = 8;
         rc = kernel_config(ln.kind, prec, ln.N, ln.contig, wide && ln.kind != KIND_COPY ? 7 : variant, &ln.cfg);
         if (ln.kind == KIND_COPY) ln.cfg.wide = wide ? 1 : 0;
     }
-    if (ln.kind == KIND_C2C && !ln.cfg.wide && !ln.cfg.xside)
+    if (ln.kind == KIND_C2C && !ln.cfg.wide && !ln.cfg.xside && !ln.cfg.alt)
         ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0) {
         if (ln.kind == KIND_R2R)
@@ -987,6 +990,7 @@ static pfft_tuning default_tuning()
     t.xcd_order = 0;
     t.stream_strided = 4;
     t.wide_offsets = 0;
+    t.radix_alt = 0;
     return t;
 }
 
@@ -1367,6 +1371,10 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
 
 // ------------------------------------------------------------- batches --
 
+// Stages that the multi-transform kernel runs (the default radix plan, both
+// sides stepping alike, 32-bit offsets, a register plan for the length).
+static bool multi_kernel(const KernelConfig &c) { return c.id >= 0 && !c.xside && !c.alt && !c.wide; }
+
 struct BatchGroup {
     int k = 0;              // launch index within each member's list
     int kind = KIND_C2C;
@@ -1446,10 +1454,10 @@ static int batch_plan(pfft_batch_s *b)
                 const Launch &ln = list[k];
                 BatchGroup *g = nullptr;
                 // a multi-transform kernel exists (not for stages whose sides step differently)
-                const bool multi = ln.kind == KIND_C2C && ln.cfg.id >= 0 && !ln.cfg.xside;
+                const bool multi = ln.kind == KIND_C2C && multi_kernel(ln.cfg);
                 if (multi)
                     for (auto &x : gs)
-                        if (x.kind == KIND_C2C && x.cfg.id >= 0 && !x.cfg.xside && x.N == ln.N && x.contig == ln.contig &&
+                        if (x.kind == KIND_C2C && multi_kernel(x.cfg) && x.N == ln.N && x.contig == ln.contig &&
                             x.cfg.id == ln.cfg.id && x.cfg.resident == ln.cfg.resident)
                             g = &x;
                 if (!g) {
@@ -1464,7 +1472,7 @@ static int batch_plan(pfft_batch_s *b)
                 g->members.push_back(m);
             }
             for (auto &g : gs) {
-                if (g.kind == KIND_C2C && g.cfg.id >= 0 && !g.cfg.xside) {
+                if (g.kind == KIND_C2C && multi_kernel(g.cfg)) {
                     int64_t nt = 0;
                     for (int m : g.members) nt += (dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd)[k].ntiles;
                     if ((int64_t)g.members.size() >= (1 << 23)) return fail(PFFT_EINVAL, "too many batch members");
@@ -1496,7 +1504,7 @@ static void batch_fill_args(pfft_batch_s *b)
     const uint8_t *dev = (const uint8_t *)b->dev;
     for (int dir = 0; dir < 2; dir++) {
         for (auto &g : b->groups[dir]) {
-            if (g.kind != KIND_C2C || g.cfg.id < 0 || g.cfg.xside) continue;
+            if (g.kind != KIND_C2C || !multi_kernel(g.cfg)) continue;
             StageArgs *args = (StageArgs *)(b->blob.data() + g.off_args);
             for (size_t mi = 0; mi < g.members.size(); mi++) {
                 const int m = g.members[mi];
@@ -1622,7 +1630,7 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
     if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 5 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1 ||
         t->xcd_order < 0 || t->xcd_order > 2 || t->stream_strided < 0 || t->stream_strided > 4 || t->wide_offsets < 0 ||
-        t->wide_offsets > 1)
+        t->wide_offsets > 1 || t->radix_alt < 0 || t->radix_alt > 3)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again
     plan->tuning = *t;
@@ -2004,7 +2012,7 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
     const uint8_t *dev = (const uint8_t *)b->dev;
     const int sign = direction == 0 ? -1 : 1;
     for (const auto &g : b->groups[direction]) {
-        if (g.kind == KIND_C2C && g.cfg.id >= 0 && !g.cfg.xside) {
+        if (g.kind == KIND_C2C && multi_kernel(g.cfg)) {
             if (g.ntiles == 0) continue;
             const StageArgs *args = (const StageArgs *)(dev + g.off_args);
             const Tile *tiles = (const Tile *)(dev + g.off_tiles);

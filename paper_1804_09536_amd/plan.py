@@ -176,8 +176,10 @@ class Plan:
         return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
 
     def set_tuning(self, **knobs):
-        """Change kernel tile shapes / grid policy (see pfft_tuning); results
-        do not change.  Drops the bound device state (rebound on next use)."""
+        """Change kernel tile shapes / grid policy / radix plan (see
+        pfft_tuning); results do not change beyond rounding (bitwise equal
+        except for radix_alt).  Drops the bound device state (rebound on next
+        use)."""
         cur = self.tuning()
         cur.update(knobs)
         t = _lib.Tuning(**cur)

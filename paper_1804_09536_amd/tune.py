@@ -5,8 +5,9 @@ JSON file (``$PFFT_TUNE_CACHE``, default ``~/.cache/paper_1804_09536_amd/tune.js
 
 The search is coordinate-wise: strided-stage knobs first (with the library
 defaults for the contiguous stages), then contiguous-stage knobs, then the
-forward and the backward placement; about 30 timed configurations per
-workload.
+XCD tile order, streaming loads/stores and the radix plan of the complex
+stages, then the forward and the backward placement; about 40 timed
+configurations per workload.
 """
 from __future__ import annotations
 
@@ -23,6 +24,8 @@ from .plan import Plan
 TILES = (0, 1, 2, 3, 4, 5)
 RESIDENT = (0, 1)
 PLACEMENTS = ("gather", "scatter", "direct", "final")
+# single knobs searched one at a time after the tile shapes
+KNOBS = (("xcd_order", (0, 1, 2)), ("stream_strided", (0, 1, 2, 3, 4)), ("radix_alt", (0, 1, 2, 3)))
 
 
 def cache_path() -> str:
@@ -115,6 +118,14 @@ def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None,
                 ms = run(t)
                 if ms < ms_cur:
                     cur, ms_cur = t, ms
+    for name, values in KNOBS:
+        for v in values:
+            t = dict(cur, **{name: v})
+            if t == cur:
+                continue
+            ms = run(t)
+            if ms < ms_cur:
+                cur, ms_cur = t, ms
     del case, plan
     chosen = []
     for side in (0, 1):

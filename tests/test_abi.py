@@ -194,6 +194,22 @@ def test_forced_wide_offsets_validate(shape, grid, kind):
     p.validate()
 
 
+@pytest.mark.parametrize("alt", [1, 2, 3])
+@pytest.mark.parametrize("shape,grid,tr", [((32, 48, 4096), (2, 3), False), ((3072, 4, 64), (4, 2), False),
+                                           ((96, 128, 192), (2, 2), True), ((512, 512, 512), (8, 8), False)])
+def test_radix_alt_plans_validate(shape, grid, tr, alt):
+    # the alternative radix plan changes the stage kernels' tile shapes only
+    # through their thread counts: the address emulation still covers every
+    # destination element once
+    from paper_1804_09536_amd.plan import Plan
+    p = Plan(shape, grid, transposed_out=tr, device="cpu")
+    p.set_tuning(radix_alt=alt)
+    assert p.tuning()["radix_alt"] == alt
+    p.validate()
+    with pytest.raises(_lib.PfftError):
+        p.set_tuning(radix_alt=4)
+
+
 def test_weighted_energy_argument_checks():
     # checked before anything is launched, so no device is needed
     lib = _lib.load()

@@ -41,6 +41,8 @@ PLAN_DRIVER = textwrap.dedent("""
         p.validate()
         p.set_tuning(tile_strided=2, xcd_order=1, wide_offsets=1)
         p.validate()
+        p.set_tuning(tile_strided=5, xcd_order=0, wide_offsets=0, radix_alt=3)
+        p.validate()
         n += 1
     for path in ("unfused", "pack_realign"):
         Plan((8, 12, 16), (2, 3), path=path, destroy_input=True, device="cpu").validate()
