@@ -198,8 +198,9 @@ typedef struct {
     int resident_contig;
     int resident_strided;
     int xcd_order;  /* complex strided stages launched one tile per workgroup: 0 by the plan's rule
-                       (stages that store straight into a layout splitting their axis, unwrapped
-                       tiles, lines up to 512 points, destinations beyond 256 MiB), 1 always, 2 never.
+                       (unwrapped tiles of stages that store straight into a layout splitting their
+                       axis, lines up to 512 points, destinations beyond 256 MiB; and unwrapped tiles
+                       whose rows are narrower than 128 bytes, the long lines), 1 always, 2 never.
                        With it, each of the 8 XCDs (workgroup b runs on XCD b mod 8) takes one
                        contiguous range of tiles. */
     int stream_strided; /* complex strided stages, full tiles: 0 ordinary loads and stores, 1 streaming
