@@ -347,10 +347,14 @@ struct LdsTile {
 // transform's output point jt + m*TPL.  The LDS holds WL lines: with H > 1
 // portions, slots [h*NL/H, (h+1)*NL/H) (lines [h*WL, (h+1)*WL)) exchange in
 // turn, so a tile of H*WL lines needs the LDS of WL lines.
-// ALT selects the alternative radix plan (fft_p2_alt).
-template <typename T2, int N, int WL, bool CONTIG, int SIGN, int NL, int H, int PASS, int ALT = 0>
+// ALT selects the alternative radix plan (fft_p2_alt).  With HS > 1
+// portions over line slots instead (H = 1): the slots of the tile form HS
+// groups, the thread's slot group is `grp`, and wl holds the thread's lines
+// numbered inside its group (the LDS then holds WL = W / HS lines); group h
+// exchanges in turn h, every line of its threads at once.
+template <typename T2, int N, int WL, bool CONTIG, int SIGN, int NL, int H, int PASS, int ALT = 0, int HS = 1>
 __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points_a(N, ALT)], const int (&wl)[NL], int jt, T2 *lds,
-                                           const T2 *__restrict__ tw)
+                                           const T2 *__restrict__ tw, int grp = 0)
 {
     constexpr int P = fft_points_a(N, ALT);
     constexpr int NP = fft_npasses_a(N, ALT);
@@ -359,10 +363,32 @@ __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points_a(N, ALT)], co
     constexpr int TPL = N / P;
     constexpr int NLH = NL / H;
     static_assert(NL % H == 0, "portions must split the line slots evenly");
+    static_assert(HS == 1 || H == 1, "portions over lines or over slots, not both");
     using LT = LdsTile<T2, N, WL, CONTIG>;
 #pragma unroll
     for (int l = 0; l < NL; l++) pass_butterflies<T2, N, P, R, L, SIGN>(v[l], jt, tw);
-    if constexpr (PASS + 1 < NP) {
+    if constexpr (PASS + 1 < NP && HS > 1) {
+        for (int h = 0; h < HS; h++) {
+            if (PASS > 0 || h > 0) __syncthreads();
+            if (grp == h) {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int b = 0; b < P / R; b++)
+#pragma unroll
+                        for (int s = 0; s < R; s++)
+                            lds[LT::idx(wl[l], pass_out_index<N, P, R, L>(jt, b, s))] = v[l][b + s * (P / R)];
+            }
+            __syncthreads();
+            if (grp == h) {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l], jt + m * TPL)];
+            }
+        }
+        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1, ALT, HS>(v, wl, jt, lds, tw, grp);
+    } else if constexpr (PASS + 1 < NP) {
 #pragma unroll
         for (int h = 0; h < H; h++) {
             if (PASS > 0 || h > 0) __syncthreads();
@@ -380,7 +406,7 @@ __device__ __forceinline__ void fft_passes(T2 (&v)[NL][fft_points_a(N, ALT)], co
 #pragma unroll
                 for (int m = 0; m < P; m++) v[l][m] = lds[LT::idx(wl[l] - h * WL, jt + m * TPL)];
         }
-        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1, ALT>(v, wl, jt, lds, tw);
+        fft_passes<T2, N, WL, CONTIG, SIGN, NL, H, PASS + 1, ALT, HS>(v, wl, jt, lds, tw, grp);
     }
 }
 

@@ -22,9 +22,10 @@
 
 namespace pfft {
 
-template <typename T, int N, bool CONTIG, int W_, int NL_, int H_ = 1, int ALT_ = 0>
+template <typename T, int N, bool CONTIG, int W_, int NL_, int H_ = 1, int ALT_ = 0, int HS_ = 1>
 struct C2CCfg {
     static constexpr int ALT = ALT_;                                 // alternative radix plan
+    static constexpr int HS = HS_;                                   // LDS portions over slot groups
     static constexpr int P = fft_points_a(N, ALT_);
     static constexpr int TPL = N / P;                                // threads per line slot
     static constexpr int VEC = (!CONTIG && sizeof(T) == 4) ? 2 : 1;  // lines per access
@@ -33,9 +34,10 @@ struct C2CCfg {
     static constexpr int SLOTS = W / NL;                             // line slots per pass
     static constexpr int NT = TPL * SLOTS;                           // threads per workgroup
     static constexpr int H = H_;                                     // LDS portions per exchange
-    static constexpr int WL = W / H;                                 // lines held in LDS at once
+    static constexpr int WL = W / (H * HS_);                         // lines held in LDS at once
     static_assert(W % NL == 0 && NL % VEC == 0, "tile shape");
     static_assert(NL % H == 0 && W % H == 0 && (NL / H) % VEC == 0, "LDS portions");
+    static_assert(HS_ == 1 || (H_ == 1 && !CONTIG && SLOTS % HS_ == 0), "slot-group portions");
     static_assert(NT <= 1024, "workgroup too large");
 };
 
@@ -72,6 +74,11 @@ struct C2CWorker {
 
     int jt, slot;
     int wl[NL];
+    // with portions over slot groups: the thread's group and its lines
+    // numbered inside the group (the LDS rows it uses)
+    static constexpr int SPG = SLOTS / S::HS;
+    int grp = 0;
+    int wg[S::HS > 1 ? NL : 1];
 
     // Make the thread geometry opaque to the optimiser once per tile, so the
     // per-position LDS offsets and twiddle indices are recomputed instead of
@@ -81,6 +88,10 @@ struct C2CWorker {
         asm volatile("" : "+v"(jt));
 #pragma unroll
         for (int l = 0; l < NL; l++) asm volatile("" : "+v"(wl[l]));
+        if constexpr (S::HS > 1) {
+#pragma unroll
+            for (int l = 0; l < NL; l++) asm volatile("" : "+v"(wg[l]));
+        }
     }
 
     __device__ __forceinline__ void init_geometry()
@@ -99,6 +110,11 @@ struct C2CWorker {
                 wl[l] = slot + l * SLOTS;
             else
                 wl[l] = (slot + (l / VEC) * SLOTS) * VEC + (l % VEC);
+        }
+        if constexpr (S::HS > 1) {
+            grp = slot / SPG;
+#pragma unroll
+            for (int l = 0; l < NL; l++) wg[l] = (slot % SPG + (l / VEC) * SPG) * VEC + (l % VEC);
         }
     }
 
@@ -187,7 +203,10 @@ struct C2CWorker {
                                             const SideAddr<P, Off> &dst, int count, T2 *lds, const T2 *tw) const
     {
         if constexpr (fft_npasses_a(N, S::ALT) > 1) __syncthreads();  // the previous tile's last LDS reads are done
-        fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0, S::ALT>(v, wl, jt, lds, tw);
+        if constexpr (S::HS > 1)
+            fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, 1, 0, S::ALT, S::HS>(v, wg, jt, lds, tw, grp);
+        else
+            fft_passes<T2, N, S::WL, CONTIG, SIGN, NL, S::H, 0, S::ALT>(v, wl, jt, lds, tw);
         const T scale = (T)a.scale;
         if (scale != (T)1) {
 #pragma unroll
@@ -263,7 +282,7 @@ struct C2CWorker {
 template <class S, typename Off = int>
 constexpr int c2c_waves_per_eu()
 {
-    return (S::NT == 512 && S::H > 1 && sizeof(Off) == 4) ? 4 : 1;
+    return (S::NT == 512 && (S::H > 1 || S::HS > 1) && sizeof(Off) == 4) ? 4 : 1;
 }
 
 // Twiddle table of the stage staged in LDS once per workgroup (the passes

@@ -2,6 +2,8 @@
 // shapes of k_c2c.
 #pragma once
 
+#include <type_traits>
+
 #include "k_c2c.hpp"
 #include "pfft_kernels.hpp"
 
@@ -56,6 +58,41 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
     return hipGetLastError();
 }
 
+// Long strided lines (1024 points and more): NTT threads, one pair (complex64)
+// or one line (complex128) per thread and slot (at most 12 points per
+// thread: the alternative radix plans of 8 and 12), so a tile is as wide as the
+// thread count allows (W = VEC * NTT / TPL lines); the LDS exchanges in the
+// fewest slot-group portions whose rows fit two workgroups per CU at 512
+// threads, one at 1024.  Variant 9: 512 threads, 10: 1024.
+template <typename T, int N, int NTT>
+struct C2CLong {
+    using T2 = typename V2<T>::type;
+    static constexpr int VEC = sizeof(T) == 4 ? 2 : 1;
+    static constexpr int ESZ = 2 * (int)sizeof(T);
+    // lengths of 16 or 24 points per thread take their alternative plan (8, 12)
+    static constexpr int ALT = (fft_points(N) > 12 && fft_p2_alt(N) != fft_p2(N)) ? 1 : 0;
+    static constexpr int TPL = N / fft_points_a(N, ALT);
+    static constexpr int SLOTS = TPL <= NTT ? NTT / TPL : 0;
+    static constexpr int W = SLOTS * VEC;
+    static constexpr int PADW = PFFT_STRIDED_PAD_BYTES / ESZ;
+    static constexpr int CAP = (NTT <= 512 ? 79 : 158) * 1024 - (TwiddleStage<T2, N>::on ? N * ESZ : 0);
+    static constexpr int lds_bytes(int hs) { return N * (W / hs + PADW) * ESZ; }
+    static constexpr int pick(int hs) { return hs > SLOTS ? 0 : (lds_bytes(hs) <= CAP ? hs : pick(hs * 2)); }
+    static constexpr int HS = SLOTS > 0 ? pick(1) : 0;
+    static constexpr bool exists = N >= 1024 && fft_npasses(N) > 1 && HS >= 1 && SLOTS % (HS > 0 ? HS : 1) == 0;
+    using type = C2CCfg<T, N, false, exists ? W : VEC, VEC, 1, ALT, exists ? HS : 1>;
+};
+
+template <typename T, int N, int SIGN, int NTT>
+static hipError_t c2c_launch_long(const KernelConfig &c, const StageArgs &a, hipStream_t s)
+{
+    using S = typename C2CLong<T, N, NTT>::type;
+    (void)c;
+    long g = a.ntiles < 1 ? 1 : a.ntiles;
+    hipLaunchKernelGGL((k_c2c<T, N, false, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
 // The alternative radix plan with the measured default tile shape of the
 // mode (lines per tile and LDS portions of that shape, lines per thread
 // chosen for at most 512 threads).
@@ -84,10 +121,15 @@ static hipError_t c2c_launch_alt(const KernelConfig &c, const StageArgs &a, hipS
 
 // The stage whose destination lines step the other way (XS), with the
 // measured default tile shape of the kernel's mode.
+// Strided lines of 1536 points and more take the long-line shapes (512
+// threads at 1536, 1024 beyond), as in the plan's rule.
 template <typename T, int N, bool CONTIG>
 struct C2CXsShape {
     static constexpr int V = C2CVariant<T, N, CONTIG, CONTIG ? 1 : 3>::exists ? (CONTIG ? 1 : 3) : 0;
-    using type = typename C2CVariant<T, N, CONTIG, V>::type;
+    static constexpr int NTT = N == 1536 ? 512 : 1024;
+    static constexpr bool use_long = !CONTIG && N >= 1536 && C2CLong<T, N, NTT>::exists;
+    using type = typename std::conditional<use_long, typename C2CLong<T, N, NTT>::type,
+                                           typename C2CVariant<T, N, CONTIG, V>::type>::type;
 };
 
 template <typename T, int N, bool CONTIG, int SIGN>
@@ -164,6 +206,12 @@ static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStr
         if constexpr (C2CAlt<T, N, CONTIG>::exists) return c2c_launch_alt<T, N, CONTIG, SIGN>(c, a, s);
     }
     switch (c.id) {
+    case 9:
+        if constexpr (!CONTIG && C2CLong<T, N, 512>::exists) return c2c_launch_long<T, N, SIGN, 512>(c, a, s);
+        break;
+    case 10:
+        if constexpr (!CONTIG && C2CLong<T, N, 1024>::exists) return c2c_launch_long<T, N, SIGN, 1024>(c, a, s);
+        break;
     case 1:
         if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
         break;
@@ -192,6 +240,25 @@ static void c2c_cfg_mode(int variant, KernelConfig *c)
             c->id = 8;
             c->alt = 1;
             return;
+        }
+        variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
+    }
+    if (variant == 9 || variant == 10) {  // long strided lines, 512 or 1024 threads
+        if constexpr (!CONTIG && C2CLong<T, N, 512>::exists) {
+            if (variant == 9) {
+                c->W = C2CLong<T, N, 512>::type::W;
+                c->threads = C2CLong<T, N, 512>::type::NT;
+                c->id = 9;
+                return;
+            }
+        }
+        if constexpr (!CONTIG && C2CLong<T, N, 1024>::exists) {
+            if (variant == 10) {
+                c->W = C2CLong<T, N, 1024>::type::W;
+                c->threads = C2CLong<T, N, 1024>::type::NT;
+                c->id = 10;
+                return;
+            }
         }
         variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
     }

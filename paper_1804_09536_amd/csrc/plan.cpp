@@ -673,9 +673,17 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     int variant = (ln.kind == KIND_C2C || ln.kind == KIND_R2C || ln.kind == KIND_C2R || ln.kind == KIND_R2R)
                       ? (ln.contig ? tu.tile_contig : tu.tile_strided)
                       : 0;
-    // 5: the measured choice per length (wider tiles for long strided lines;
-    // real-to-real stages are fastest with more, smaller workgroups)
-    if (variant == 5) variant = (ln.contig || ln.kind == KIND_R2R) ? 1 : (ln.N >= 1024 ? 4 : 3);
+    // 5: the measured choice per length (wider tiles for long strided lines,
+    // the long-line shapes from 1536 points: 512 threads at 1536, 1024
+    // beyond; real-to-real stages are fastest with more, smaller workgroups)
+    if (variant == 5)
+        variant = (ln.contig || ln.kind == KIND_R2R) ? 1
+                  : ln.N < 1024                      ? 3
+                  : ln.N == 1024                     ? 4
+                  : ln.N == 1536                     ? 6
+                                                     : 7;
+    // 6 / 7: the long-line shapes of complex strided stages (512 / 1024 threads)
+    if (variant == 6 || variant == 7) variant = (ln.kind == KIND_C2C && !ln.contig) ? variant + 3 : 0;
     int rc;
     if (ln.mixed_sides && ln.kind != KIND_COPY) {
         // lines contiguous on one side and adjacent on the other: the stage
@@ -694,7 +702,7 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         rc = kernel_config(ln.kind, prec, ln.N, ln.contig, wide && ln.kind != KIND_COPY ? 7 : variant, &ln.cfg);
         if (ln.kind == KIND_COPY) ln.cfg.wide = wide ? 1 : 0;
     }
-    if (ln.kind == KIND_C2C && !ln.cfg.wide && !ln.cfg.xside && !ln.cfg.alt)
+    if (ln.kind == KIND_C2C && !ln.cfg.wide && !ln.cfg.xside && !ln.cfg.alt && ln.cfg.id <= 4)
         ln.cfg.resident = ln.contig ? tu.resident_contig : tu.resident_strided;
     if (rc != 0) {
         if (ln.kind == KIND_R2R)
@@ -1380,7 +1388,7 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
 
 // Stages that the multi-transform kernel runs (the default radix plan, both
 // sides stepping alike, 32-bit offsets, a register plan for the length).
-static bool multi_kernel(const KernelConfig &c) { return c.id >= 0 && !c.xside && !c.alt && !c.wide; }
+static bool multi_kernel(const KernelConfig &c) { return c.id >= 0 && c.id <= 4 && !c.xside && !c.alt && !c.wide; }
 
 struct BatchGroup {
     int k = 0;              // launch index within each member's list
@@ -1634,7 +1642,7 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
 {
     PFFT_GUARD_BEGIN
     if (!plan || !t) return fail(PFFT_EINVAL, "null argument");
-    if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 5 ||
+    if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 7 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1 ||
         t->xcd_order < 0 || t->xcd_order > 2 || t->stream_strided < 0 || t->stream_strided > 4 || t->wide_offsets < 0 ||
         t->wide_offsets > 1 || t->radix_alt < 0 || t->radix_alt > 3)

@@ -141,6 +141,27 @@ def test_c2c_long_lengths(N, mode, prec):
     assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= TOL[prec]
 
 
+# The long-line shapes of strided stages (tile_strided 6: 512 threads, 7:
+# 1024; slot-group LDS portions), on full and wrapped tiles and a ragged
+# cross-section.
+@pytest.mark.parametrize("ts", [6, 7])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("N", [1024, 1536, 2048, 3072, 4096])
+def test_c2c_long_strided_shapes(N, prec, ts):
+    for shape, grid in [((N, 8, 16), (4, 2)), ((N, 5, 33), (2, 3))]:
+        print("case", shape, grid, prec, ts, flush=True)
+        p = Plan(shape, grid, precision=prec)
+        p.set_tuning(tile_strided=ts)
+        ch = oracle.Chain.paper(shape, grid)
+        n = p.buffer_numel(0)
+        u = inputs.uniform_complex(n, [23, N, ts], NPDT[prec])
+        y = p.forward(_to_dev(u))
+        got = _host(y)
+        assert relerr(got, oracle.forward(ch, u.astype(np.complex128))) <= TOL[prec]
+        z = _host(p.backward(y))
+        assert relerr(z, oracle.backward(ch, got.astype(np.complex128))) <= TOL[prec]
+
+
 @pytest.mark.parametrize("norm", ["backward", "none"])
 def test_c2c_other_norms(norm):
     shape, grid = (32, 16, 64), (2, 4)
