@@ -58,35 +58,46 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
     return hipGetLastError();
 }
 
-// Long strided lines (1024 points and more): NTT threads, one pair (complex64)
-// or one line (complex128) per thread and slot (at most 12 points per
-// thread: the alternative radix plans of 8 and 12), so a tile is as wide as the
-// thread count allows (W = VEC * NTT / TPL lines); the LDS exchanges in the
-// fewest slot-group portions whose rows fit two workgroups per CU at 512
-// threads, one at 1024.  Variant 9: 512 threads, 10: 1024.
-template <typename T, int N, int NTT>
-struct C2CLong {
+// Slot-group shapes of strided stages: NTT threads, NLM line pairs
+// (complex64) or lines (complex128) per thread and slot, at most 12 points
+// per thread (lengths of 16 or 24 take their alternative plans of 8 and 12),
+// so a tile is as wide as the thread count allows (W = NLM * VEC * NTT / TPL
+// lines); the LDS exchanges in the fewest slot-group portions whose rows fit
+// WGS workgroups per CU.  Variants (tile_strided value in brackets):
+//   9 (6):  512 threads, two workgroups per CU, lines of 1024 points and more
+//   10 (7): 1024 threads, one workgroup per CU, lines of 1024 points and more
+// (Wider tiles of this kind -- 1024 threads with one or two pairs per slot --
+// measured 1.2-3x slower than the default shapes on lines of 256-768 points.)
+template <typename T, int N, int NTT, int NLM, int WGS, int NMIN>
+struct C2CSlotShape {
     using T2 = typename V2<T>::type;
     static constexpr int VEC = sizeof(T) == 4 ? 2 : 1;
     static constexpr int ESZ = 2 * (int)sizeof(T);
-    // lengths of 16 or 24 points per thread take their alternative plan (8, 12)
     static constexpr int ALT = (fft_points(N) > 12 && fft_p2_alt(N) != fft_p2(N)) ? 1 : 0;
     static constexpr int TPL = N / fft_points_a(N, ALT);
     static constexpr int SLOTS = TPL <= NTT ? NTT / TPL : 0;
-    static constexpr int W = SLOTS * VEC;
+    static constexpr int NL = NLM * VEC;
+    static constexpr int W = SLOTS * NL;
     static constexpr int PADW = PFFT_STRIDED_PAD_BYTES / ESZ;
-    static constexpr int CAP = (NTT <= 512 ? 79 : 158) * 1024 - (TwiddleStage<T2, N>::on ? N * ESZ : 0);
+    static constexpr int CAP = 158 * 1024 / WGS - (TwiddleStage<T2, N>::on ? N * ESZ : 0);
     static constexpr int lds_bytes(int hs) { return N * (W / hs + PADW) * ESZ; }
     static constexpr int pick(int hs) { return hs > SLOTS ? 0 : (lds_bytes(hs) <= CAP ? hs : pick(hs * 2)); }
     static constexpr int HS = SLOTS > 0 ? pick(1) : 0;
-    static constexpr bool exists = N >= 1024 && fft_npasses(N) > 1 && HS >= 1 && SLOTS % (HS > 0 ? HS : 1) == 0;
-    using type = C2CCfg<T, N, false, exists ? W : VEC, VEC, 1, ALT, exists ? HS : 1>;
+    static constexpr bool exists = N >= NMIN && fft_npasses(N) > 1 && HS >= 1 && SLOTS % (HS > 0 ? HS : 1) == 0;
+    using type = C2CCfg<T, N, false, exists ? W : VEC, exists ? NL : VEC, 1, ALT, exists ? HS : 1>;
 };
 
-template <typename T, int N, int SIGN, int NTT>
-static hipError_t c2c_launch_long(const KernelConfig &c, const StageArgs &a, hipStream_t s)
+template <typename T, int N, int ID>
+struct C2CSlot;
+template <typename T, int N>
+struct C2CSlot<T, N, 9> : C2CSlotShape<T, N, 512, 1, 2, 1024> {};
+template <typename T, int N>
+struct C2CSlot<T, N, 10> : C2CSlotShape<T, N, 1024, 1, 1, 1024> {};
+
+template <typename T, int N, int SIGN, int ID>
+static hipError_t c2c_launch_slot(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
-    using S = typename C2CLong<T, N, NTT>::type;
+    using S = typename C2CSlot<T, N, ID>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
     hipLaunchKernelGGL((k_c2c<T, N, false, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
@@ -126,9 +137,9 @@ static hipError_t c2c_launch_alt(const KernelConfig &c, const StageArgs &a, hipS
 template <typename T, int N, bool CONTIG>
 struct C2CXsShape {
     static constexpr int V = C2CVariant<T, N, CONTIG, CONTIG ? 1 : 3>::exists ? (CONTIG ? 1 : 3) : 0;
-    static constexpr int NTT = N == 1536 ? 512 : 1024;
-    static constexpr bool use_long = !CONTIG && N >= 1536 && C2CLong<T, N, NTT>::exists;
-    using type = typename std::conditional<use_long, typename C2CLong<T, N, NTT>::type,
+    static constexpr int ID = N == 1536 ? 9 : 10;
+    static constexpr bool use_long = !CONTIG && N >= 1536 && C2CSlot<T, N, ID>::exists;
+    using type = typename std::conditional<use_long, typename C2CSlot<T, N, ID>::type,
                                            typename C2CVariant<T, N, CONTIG, V>::type>::type;
 };
 
@@ -207,10 +218,10 @@ static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStr
     }
     switch (c.id) {
     case 9:
-        if constexpr (!CONTIG && C2CLong<T, N, 512>::exists) return c2c_launch_long<T, N, SIGN, 512>(c, a, s);
+        if constexpr (!CONTIG && C2CSlot<T, N, 9>::exists) return c2c_launch_slot<T, N, SIGN, 9>(c, a, s);
         break;
     case 10:
-        if constexpr (!CONTIG && C2CLong<T, N, 1024>::exists) return c2c_launch_long<T, N, SIGN, 1024>(c, a, s);
+        if constexpr (!CONTIG && C2CSlot<T, N, 10>::exists) return c2c_launch_slot<T, N, SIGN, 10>(c, a, s);
         break;
     case 1:
         if constexpr (C2CVariant<T, N, CONTIG, 1>::exists) return c2c_launch_v<T, N, CONTIG, SIGN, 1>(c, a, s);
@@ -229,6 +240,20 @@ static hipError_t c2c_launch_s(const KernelConfig &c, const StageArgs &a, hipStr
     return c2c_launch_v<T, N, CONTIG, SIGN, 0>(c, a, s);
 }
 
+template <typename T, int N, int ID>
+static bool c2c_slot_cfg(int variant, KernelConfig *c)
+{
+    if constexpr (C2CSlot<T, N, ID>::exists) {
+        if (variant == ID) {
+            c->W = C2CSlot<T, N, ID>::type::W;
+            c->threads = C2CSlot<T, N, ID>::type::NT;
+            c->id = ID;
+            return true;
+        }
+    }
+    return false;
+}
+
 template <typename T, int N, bool CONTIG>
 static void c2c_cfg_mode(int variant, KernelConfig *c)
 {
@@ -243,22 +268,9 @@ static void c2c_cfg_mode(int variant, KernelConfig *c)
         }
         variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
     }
-    if (variant == 9 || variant == 10) {  // long strided lines, 512 or 1024 threads
-        if constexpr (!CONTIG && C2CLong<T, N, 512>::exists) {
-            if (variant == 9) {
-                c->W = C2CLong<T, N, 512>::type::W;
-                c->threads = C2CLong<T, N, 512>::type::NT;
-                c->id = 9;
-                return;
-            }
-        }
-        if constexpr (!CONTIG && C2CLong<T, N, 1024>::exists) {
-            if (variant == 10) {
-                c->W = C2CLong<T, N, 1024>::type::W;
-                c->threads = C2CLong<T, N, 1024>::type::NT;
-                c->id = 10;
-                return;
-            }
+    if (variant == 9 || variant == 10) {  // the slot-group shapes of strided stages
+        if constexpr (!CONTIG) {
+            if (c2c_slot_cfg<T, N, 9>(variant, c) || c2c_slot_cfg<T, N, 10>(variant, c)) return;
         }
         variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
     }

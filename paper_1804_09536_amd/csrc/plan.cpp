@@ -682,7 +682,7 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
                   : ln.N == 1024                     ? 4
                   : ln.N == 1536                     ? 6
                                                      : 7;
-    // 6 / 7: the long-line shapes of complex strided stages (512 / 1024 threads)
+    // 6 / 7: the slot-group shapes of complex strided stages (kernel variants 9 / 10)
     if (variant == 6 || variant == 7) variant = (ln.kind == KIND_C2C && !ln.contig) ? variant + 3 : 0;
     int rc;
     if (ln.mixed_sides && ln.kind != KIND_COPY) {
