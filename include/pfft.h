@@ -181,8 +181,9 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * default LDS in two portions (wider rows at the default LDS size), 4 four
  * times as many with 1024-thread workgroups exchanged in two portions
  * (widest rows, one workgroup per CU), 5 chosen by stage (1 for contiguous
- * and real-to-real stages; 3 for strided lines below 1024 points, 4 from
- * 1024 on: the measured best, and the default of tile_strided); tile_strided
+ * and real-to-real stages; 3 for strided lines below 1024 points, 4 at 1024,
+ * 6 at 1536, 7 from 2048 on: the measured best, and the default of
+ * tile_strided); tile_strided
  * 6 / 7: for complex lines of 1024 points and more, 512 / 1024 threads with
  * one line pair (complex64) or line (complex128) per thread and slot, the
  * LDS exchanging slot groups in turn; lengths without a shape use the
@@ -190,7 +191,9 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * workgroups as the device holds at once, each looping over tiles, 0 one
  * workgroup per tile.  *_contig applies to partial transforms along the last
  * axis (tile_contig also to the real-to-complex and complex-to-real stages,
- * which have shapes 0 and 1 only), *_strided to the others.  Strided tiles
+ * which have shapes 0, 1 and 2 = a quarter of the default lines, one line per
+ * slot; by rule real-to-complex stages take 2, complex-to-real 1), *_strided
+ * to the others.  Strided tiles
  * continue over consecutive short runs of lines (inner extents below the
  * tile width) where the blocks allow it.  xcd_order: see the field.  pfft_plan_set_tuning rebuilds the plan's
  * tables: query pfft_device_state_bytes again and bind again before use.

@@ -11,6 +11,8 @@
 // over the Hermitian extension of X (unnormalised).
 // Flags turn them into each other's adjoints: SF_DOUBLE_INTERIOR doubles the
 // r2c output bins 0 < k < M; SF_HALVE_INTERIOR halves the c2r input bins.
+#include <type_traits>
+
 #include "fft_device.hpp"
 #include "k_c2c_impl.hpp"
 #include "pfft_kernels.hpp"
@@ -229,25 +231,36 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
         X(192) X(384) X(768) X(1536) X(3072) X(6144)
 
 // Launch shapes: variant 1 (half the lines per tile) where it exists, else
-// the default.
+// the default; variant 2 a quarter of the default lines, one line per slot
+// (more, smaller workgroups per CU).
+template <typename T, int NR>
+struct RealQuarter {
+    using D = C2CDefault<T, NR / 2, true>;
+    static constexpr int W = D::W / 4 >= 1 ? D::W / 4 : 1;
+    static constexpr bool exists = D::W >= 4 && D::TPL * W <= 1024;
+    using type = C2CCfg<T, NR / 2, true, W, 1>;
+};
 template <typename T, int NR>
 struct RealShape {
     static constexpr bool half = C2CVariant<T, NR / 2, true, 1>::exists;
     template <int V>
-    using type = typename C2CVariant<T, NR / 2, true, (V == 1 && half) ? 1 : 0>::type;
+    using type = typename std::conditional<V == 2 && RealQuarter<T, NR>::exists, typename RealQuarter<T, NR>::type,
+                                           typename C2CVariant<T, NR / 2, true, (V == 1 && half) ? 1 : 0>::type>::type;
 };
 
 template <typename T>
 static int real_config_t(int NR, int variant, KernelConfig *cfg)
 {
     // variant 7: the 64-bit-offset kernel with the default shape (1)
-    const int v = (variant == 1 || variant == 7) ? 1 : 0;
+    const int v = (variant == 1 || variant == 7) ? 1 : variant == 2 ? 2 : 0;
     cfg->wide = variant == 7;
     switch (NR) {
 #define PFFT_CASE(n)                                                                              \
     case n:                                                                                       \
-        cfg->W = v ? RealShape<T, n>::template type<1>::W : RealShape<T, n>::template type<0>::W;   \
-        cfg->threads = v ? RealShape<T, n>::template type<1>::NT : RealShape<T, n>::template type<0>::NT; \
+        cfg->W = v == 2 ? RealShape<T, n>::template type<2>::W                                      \
+                        : (v ? RealShape<T, n>::template type<1>::W : RealShape<T, n>::template type<0>::W);   \
+        cfg->threads = v == 2 ? RealShape<T, n>::template type<2>::NT                               \
+                        : (v ? RealShape<T, n>::template type<1>::NT : RealShape<T, n>::template type<0>::NT); \
         cfg->id = v;                                                                              \
         return 0;
         PFFT_FOR_EACH_NR(PFFT_CASE)
@@ -276,7 +289,9 @@ static hipError_t real_launch_t(int NR, int kind, int variant, int wide, const S
 #define PFFT_CASE(n)                                                                      \
     case n:                                                                               \
         return wide ? real_launch_v<T, n, 1, long>(kind, a, s)                            \
-                    : (variant == 1 ? real_launch_v<T, n, 1>(kind, a, s) : real_launch_v<T, n, 0>(kind, a, s));
+                    : (variant == 1   ? real_launch_v<T, n, 1>(kind, a, s)                  \
+                       : variant == 2 ? real_launch_v<T, n, 2>(kind, a, s)                  \
+                                      : real_launch_v<T, n, 0>(kind, a, s));
         PFFT_FOR_EACH_NR(PFFT_CASE)
 #undef PFFT_CASE
     default:

@@ -675,9 +675,12 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
                       : 0;
     // 5: the measured choice per length (wider tiles for long strided lines,
     // the long-line shapes from 1536 points: 512 threads at 1536, 1024
-    // beyond; real-to-real stages are fastest with more, smaller workgroups)
+    // beyond; real-to-real stages are fastest with more, smaller workgroups,
+    // real-to-complex stages with a quarter of the default lines per tile:
+    // 512^3 0.264 -> 0.247 ms, while complex-to-real stages lose 12 % there)
     if (variant == 5)
-        variant = (ln.contig || ln.kind == KIND_R2R) ? 1
+        variant = ln.kind == KIND_R2C                        ? 2
+                  : (ln.contig || ln.kind == KIND_R2R) ? 1
                   : ln.N < 1024                      ? 3
                   : ln.N == 1024                     ? 4
                   : ln.N == 1536                     ? 6

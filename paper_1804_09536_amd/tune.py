@@ -21,7 +21,7 @@ import torch
 from . import inputs
 from .plan import Plan
 
-TILES = (0, 1, 2, 3, 4, 5)
+TILES = {"tile_strided": (0, 1, 2, 3, 4, 5, 6, 7), "tile_contig": (0, 1, 2, 3, 4, 5)}
 RESIDENT = (0, 1)
 PLACEMENTS = ("gather", "scatter", "direct", "final")
 # single knobs searched one at a time after the tile shapes
@@ -110,7 +110,7 @@ def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None,
 
     ms_cur = run(cur)
     for fields in (("tile_strided", "resident_strided"), ("tile_contig", "resident_contig")):
-        for tile in TILES:
+        for tile in TILES[fields[0]]:
             for res in RESIDENT:
                 t = dict(cur, **{fields[0]: tile, fields[1]: res})
                 if t == cur:
