@@ -172,28 +172,37 @@ def _timeit(fn, steps, warmup):
 def bench_batch(steps, warmup):
     """168 complex64 transforms (7 shapes x 8 instances x 3 components): the
     batch (one launch per stage and kernel shape, captured in a HIP graph)
-    against one call per transform.  Returns a record."""
+    against one call per transform, the latter both with the library
+    defaults and with each shape's autotuned knobs (the user cache, else the
+    shipped table for this device).  The batch keeps the defaults: members
+    with their own tuned knobs split the grouped launches (measured slower).
+    Returns a record."""
     import torch
 
-    from paper_1804_09536_amd import inputs
+    from paper_1804_09536_amd import inputs, tune
     from paper_1804_09536_amd.plan import Batch, Plan
 
     dev = torch.device("cuda:0")
     uniq = [Plan(s, g, device=dev).bind() for s, g in BATCH_SHAPES]
+    tuned = [tune.tuned_plan(s, g, tune_missing=False, device=dev).bind() for s, g in BATCH_SHAPES]
+    n_tuned = sum(1 for p in tuned if getattr(p, "tuned", False))
     members = [p for p in uniq for _ in range(24)]
+    tuned_members = [p for p in tuned for _ in range(24)]
     batch = Batch(members, device=dev)
     for m, x in enumerate(batch.inputs):
         x.copy_(inputs.uniform_complex_device(x.numel(), 1000 + m, torch.complex64, dev))
     total_bytes = 0.0
     for p in members:
         total_bytes += 2 * 3 * 2 * p.buffer_numel(0) * 8  # fwd+bwd, 3 stages, read+write
-    work = {id(p): p.workspace() for p in uniq}
+    work = {id(p): p.workspace() for p in uniq + tuned}
 
-    def per_transform():
-        for m, p in enumerate(members):
-            p.forward(batch.inputs[m], out=batch.outputs[m], work=work[id(p)])
-        for m, p in enumerate(members):
-            p.backward(batch.outputs[m], out=batch.inputs[m], work=work[id(p)])
+    def per_transform(plans):
+        def step():
+            for m, p in enumerate(plans):
+                p.forward(batch.inputs[m], out=batch.outputs[m], work=work[id(p)])
+            for m, p in enumerate(plans):
+                p.backward(batch.outputs[m], out=batch.inputs[m], work=work[id(p)])
+        return step
 
     def batched():
         batch.forward()
@@ -212,11 +221,12 @@ def bench_batch(steps, warmup):
 
     t_graph = _timeit(graph.replay, steps, warmup)
     t_batch = _timeit(batched, steps, warmup)
-    t_plain = _timeit(per_transform, steps, warmup)
-    # the same transforms one shape at a time: 24 calls of each plan
+    t_plain = _timeit(per_transform(tuned_members), steps, warmup)
+    t_plain_default = _timeit(per_transform(members), steps, warmup)
+    # the same transforms one shape at a time (tuned knobs): 24 calls of each plan
     per_shape = {}
-    for p in uniq:
-        idx = [m for m, q in enumerate(members) if q is p]
+    for i, p in enumerate(tuned):
+        idx = [m for m, q in enumerate(members) if q is uniq[i]]
 
         def shape_step(p=p, idx=idx):
             for m in idx:
@@ -230,7 +240,8 @@ def bench_batch(steps, warmup):
     return {"workload": "7 shapes x 8 instances x 3 components c2c complex64, mixed slab/pencil grids",
             "shapes": [[list(s), list(g)] for s, g in BATCH_SHAPES],
             "batched_graph_ms": round(t_graph, 3), "batched_eager_ms": round(t_batch, 3),
-            "per_transform_ms": round(t_plain, 3), "per_shape_ms": per_shape,
+            "per_transform_ms": round(t_plain, 3), "per_transform_tuned_shapes": n_tuned,
+            "per_transform_default_knobs_ms": round(t_plain_default, 3), "per_shape_ms": per_shape,
             "algorithmic_bytes": total_bytes,
             "pct_hbm_peak": round(100.0 * total_bytes / (t_graph * 1e-3) / HBM_PEAK, 2),
             "per_transform_pct_hbm_peak": round(100.0 * total_bytes / (t_plain * 1e-3) / HBM_PEAK, 2)}

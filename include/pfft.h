@@ -126,7 +126,9 @@ enum { PFFT_NORM_FORWARD = 0, PFFT_NORM_BACKWARD = 1, PFFT_NORM_NONE = 2 };
 #define PFFT_EDTYPE (-4)       /* bad precision / kind */
 #define PFFT_EUNSUPPORTED (-5) /* a transform length with no kernel */
 #define PFFT_EWORKSPACE (-6)   /* device state not bound, or buffer too small */
-#define PFFT_EHIP (-7)         /* a HIP runtime call failed */
+#define PFFT_EHIP (-7)         /* a HIP runtime call failed (also forced for every stage launch,
+                                  without launching, when the environment variable
+                                  PFFT_FAULT_INJECT is "launch": a test of callers' error paths) */
 #define PFFT_EINTERNAL (-8)
 
 #define PFFT_MAX_DIMS 8

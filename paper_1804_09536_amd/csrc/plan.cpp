@@ -16,6 +16,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -1092,6 +1093,15 @@ static int stage_flags(const Launch &ln, int sign, int chain_flags)
     return (ln.xcd ? SF_XCD_ORDER : 0) | ((ln.stream & 1) ? SF_LOAD_NT : 0) | ((ln.stream & 2) ? SF_STORE_NT : 0);
 }
 
+// Fault injection for tests of the error path: with PFFT_FAULT_INJECT=launch
+// in the environment every stage launch reports a launch failure instead of
+// launching (nothing reaches the device).
+static bool launch_fault_injected()
+{
+    const char *e = getenv("PFFT_FAULT_INJECT");
+    return e && strcmp(e, "launch") == 0;
+}
+
 static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *dst, double scale, int sign,
                       int flags, hipStream_t stream, int direction = 4)
 {
@@ -1105,7 +1115,9 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
     }
     flags = stage_flags(ln, sign, flags);
     const StageArgs a = stage_args(p, ln, (const uint8_t *)p->dev, src, dst, scale, flags);
-    int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
+    int rc = launch_fault_injected()
+                 ? (int)hipErrorLaunchFailure
+                 : launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
     if (rc != 0) return fail(PFFT_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     if (p->profiling) {
         if (hipEventRecord(eb, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
@@ -2034,7 +2046,8 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
             if (g.ntiles == 0) continue;
             const StageArgs *args = (const StageArgs *)(dev + g.off_args);
             const Tile *tiles = (const Tile *)(dev + g.off_tiles);
-            hipError_t e = b->precision == PFFT_F32
+            hipError_t e = launch_fault_injected() ? hipErrorLaunchFailure
+                           : b->precision == PFFT_F32
                                ? c2c_launch_multi_f32(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream)
                                : c2c_launch_multi_f64(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream);
             if (e != hipSuccess) return fail(PFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
@@ -2055,7 +2068,9 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
                 assign_buffers(p, list, out, in, work, srcs, dsts);
             double scale = ln.kind == KIND_COPY ? 1.0 : axis_scale(p, ln.scale_axis, direction == 0);
             StageArgs a = stage_args(p, ln, dev + b->blob_off[m], srcs[g.k], dsts[g.k], scale, stage_flags(ln, sign, 0));
-            int rc = launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
+            int rc = launch_fault_injected()
+                         ? (int)hipErrorLaunchFailure
+                         : launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
             if (rc != 0) return fail(PFFT_EHIP, std::string("batch launch: ") + hipGetErrorString((hipError_t)rc));
         }
     }

@@ -28,6 +28,12 @@ PLACEMENTS = ("gather", "scatter", "direct", "final")
 KNOBS = (("xcd_order", (0, 1, 2)), ("stream_strided", (0, 1, 2, 3, 4)), ("radix_alt", (0, 1, 2, 3)))
 
 
+# Choices measured on MI355X for the workloads of the bench (written by
+# `python -m paper_1804_09536_amd.tune --out <this file> --case ...`), used
+# where the user cache has no entry.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+
+
 def cache_path() -> str:
     return os.environ.get("PFFT_TUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "paper_1804_09536_amd", "tune.json"))
@@ -85,6 +91,18 @@ class _Case:
         self.bwd()
 
 
+def lookup(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None, path: str = "fused",
+           cache: Optional[str] = None) -> Optional[dict]:
+    """The cached choice for the workload on this device (the user cache
+    first, then the shipped table), or None."""
+    key = _key(shape, grid, kind, precision, chain, path)
+    for path_ in (cache or cache_path(), SHIPPED):
+        table = _load_cache(path_)
+        if key in table:
+            return table[key]
+    return None
+
+
 def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None, path: str = "fused",
              steps: int = 5, cache: Optional[str] = None, force: bool = False, verbose: bool = False) -> dict:
     """Best {"placement": [forward, backward], "tuning", "ms"} for the
@@ -93,9 +111,10 @@ def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None,
     (the forward placement changes only forward launches, and likewise)."""
     cache = cache or cache_path()
     key = _key(shape, grid, kind, precision, chain, path)
-    table = _load_cache(cache)
-    if key in table and not force:
-        return table[key]
+    if not force:
+        hit = lookup(shape, grid, kind, precision, chain, path, cache)
+        if hit is not None:
+            return hit
     case = _Case(shape, grid, kind, precision, chain, path, None)
     plan = case.plan
     cur = plan.tuning()
@@ -161,10 +180,36 @@ def autotune(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None,
 
 
 def tuned_plan(shape, grid, kind: str = "c2c", precision: str = "f32", chain=None, path: str = "fused",
-               **kw) -> Plan:
-    """A plan with the cached (or freshly tuned) best knobs."""
-    best = autotune(shape, grid, kind=kind, precision=precision, chain=chain, path=path, **kw)
+               tune_missing: bool = True, device=None, **kw) -> Plan:
+    """A plan with the cached (or, with tune_missing, freshly tuned) best
+    knobs; the library defaults where there is none."""
+    best = (autotune(shape, grid, kind=kind, precision=precision, chain=chain, path=path, **kw) if tune_missing
+            else lookup(shape, grid, kind, precision, chain, path, kw.get("cache")))
+    if best is None:
+        return Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path, device=device)
     plan = Plan(shape, grid, precision=precision, kind=kind, chain=chain, path=path,
-                placement=tuple(best["placement"]))
+                placement=tuple(best["placement"]), device=device)
     plan.set_tuning(**best["tuning"])
+    plan.tuned = True
     return plan
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="tune workloads on this device and write the choices to a table")
+    ap.add_argument("--out", required=True, help="JSON table to write (entries are added or replaced)")
+    ap.add_argument("--case", action="append", required=True,
+                    help='JSON [shape, grid] or [shape, grid, kind, precision], e.g. "[[384,384,384],[8,8]]"')
+    ap.add_argument("--steps", type=int, default=5)
+    args = ap.parse_args(argv)
+    for c in args.case:
+        spec = json.loads(c)
+        shape, grid = tuple(spec[0]), tuple(spec[1])
+        kind = spec[2] if len(spec) > 2 else "c2c"
+        prec = spec[3] if len(spec) > 3 else "f32"
+        best = autotune(shape, grid, kind=kind, precision=prec, steps=args.steps, cache=args.out, force=True)
+        print(json.dumps({"shape": shape, "grid": grid, "kind": kind, "precision": prec, **best}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
