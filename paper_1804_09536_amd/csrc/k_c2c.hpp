@@ -70,7 +70,9 @@ struct C2CWorker {
     using T4 = typename V2<T>::quad;
     static constexpr int P = S::P, TPL = S::TPL, VEC = S::VEC, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
     using LT = LdsTile<T2, N, S::WL, CONTIG>;
-    static constexpr int LDS_SIZE = (fft_npasses_a(N, S::ALT) > 1) ? LT::SIZE : 1;
+    // XS stages with line portions stage their stores through the LDS tile
+    static constexpr bool XS_STAGED = XS && S::HS == 1;
+    static constexpr int LDS_SIZE = (fft_npasses_a(N, S::ALT) > 1 || XS_STAGED) ? LT::SIZE : 1;
 
     int jt, slot;
     int wl[NL];
@@ -198,6 +200,69 @@ struct C2CWorker {
         }
     }
 
+    // Store of an XS stage through the LDS tile, one portion of WL lines at a
+    // time: the transformed lines are written in the kernel's LDS layout and
+    // read back in the destination's order, so the stores coalesce.  A
+    // contiguous-mode kernel (destination lines adjacent, point j of line w at
+    // off(j) + w) stores with lanes across the lines of the portion; a
+    // strided-mode kernel (destination lines contiguous) stores with up to 64
+    // lanes along a line.
+    __device__ __forceinline__ void xs_store_staged(const StageArgs &a, const Tile &t, T2 (&v)[NL][P], int cnt,
+                                                    T2 *lds) const
+    {
+        constexpr int H = S::H, WL = S::WL, NT = S::NT, NLH = NL / H;
+        T2 *__restrict__ out = (T2 *)a.dst;
+        const int tid = threadIdx.x;
+        if constexpr (CONTIG) {
+            static_assert(NT % WL == 0 && (N * WL) % NT == 0, "staged store geometry");
+            constexpr int SJ = NT / WL;           // threads per line position set
+            constexpr int NV = N * WL / NT;       // points per thread and portion
+            const int sw = tid % WL, sj = tid / WL;
+            SideAddr<NV, Off> sd;
+            sd.init(a.side[1], t, 1, sj, SJ, N, false);
+#pragma unroll
+            for (int h = 0; h < H; h++) {
+                __syncthreads();
+#pragma unroll
+                for (int l = h * NLH; l < (h + 1) * NLH; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++) lds[LT::idx(wl[l] - h * WL, jt + m * TPL)] = v[l][m];
+                __syncthreads();
+                const int w = h * WL + sw;
+                if (w < cnt) {
+#pragma unroll
+                    for (int k = 0; k < NV; k++) out[sd.off[k] + (Off)w] = lds[LT::idx(sw, sj + k * SJ)];
+                }
+            }
+        } else {
+            constexpr int SJ = (N % 64 == 0) ? 64 : (N % 32 == 0) ? 32 : (N % 16 == 0) ? 16 : (N % 8 == 0) ? 8 : 1;
+            constexpr int LP = NT / SJ;            // lines stored per pass
+            constexpr int NV = N / SJ;             // points per thread and line
+            static_assert(NT % SJ == 0, "staged store geometry");
+            const int sj = tid % SJ, sw = tid / SJ;
+            SideAddr<NV, Off> sd;
+            sd.init(a.side[1], t, 1, sj, SJ, N, true);
+#pragma unroll
+            for (int h = 0; h < H; h++) {
+                __syncthreads();
+#pragma unroll
+                for (int l = h * NLH; l < (h + 1) * NLH; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++) lds[LT::idx(wl[l] - h * WL, jt + m * TPL)] = v[l][m];
+                __syncthreads();
+#pragma unroll
+                for (int wloc = sw; wloc < WL; wloc += LP) {
+                    const int w = h * WL + wloc;
+                    if (w < cnt) {
+#pragma unroll
+                        for (int k = 0; k < NV; k++) out[sd.off[k] + (Off)w * sd.stride[k]] = lds[LT::idx(wloc, sj + k * SJ)];
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the LDS reads are done before any later use of the tile
+    }
+
     // Transform the registers of one tile (LDS-staged passes), scale, store.
     __device__ __forceinline__ void process(const StageArgs &a, const Tile &t, T2 (&v)[NL][P],
                                             const SideAddr<P, Off> &dst, int count, T2 *lds, const T2 *tw) const
@@ -215,6 +280,10 @@ struct C2CWorker {
                 for (int m = 0; m < P; m++) v[l][m] = c_scale(v[l][m], scale);
         }
         T2 *__restrict__ out = (T2 *)a.dst;
+        if constexpr (XS_STAGED) {
+            xs_store_staged(a, t, v, count > 0 ? count : -count, lds);
+            return;
+        }
         if constexpr (XS) {
             // line w of the destination at dst.off[m] + w * dst.stride[m]
             const int cnt = count > 0 ? count : -count;

@@ -130,17 +130,31 @@ static hipError_t c2c_launch_alt(const KernelConfig &c, const StageArgs &a, hipS
     return hipGetLastError();
 }
 
-// The stage whose destination lines step the other way (XS), with the
-// measured default tile shape of the kernel's mode.
-// Strided lines of 1536 points and more take the long-line shapes (512
-// threads at 1536, 1024 beyond), as in the plan's rule.
+// The stage of plans with buffers of 2^31 elements or more, with the
+// measured default tile shape of the kernel's mode; strided lines of 1536
+// points and more take the long-line shapes (512 threads at 1536, 1024
+// beyond), as in the plan's rule.
 template <typename T, int N, bool CONTIG>
-struct C2CXsShape {
+struct C2CWideShape {
     static constexpr int V = C2CVariant<T, N, CONTIG, CONTIG ? 1 : 3>::exists ? (CONTIG ? 1 : 3) : 0;
     static constexpr int ID = N == 1536 ? 9 : 10;
     static constexpr bool use_long = !CONTIG && N >= 1536 && C2CSlot<T, N, ID>::exists;
     using type = typename std::conditional<use_long, typename C2CSlot<T, N, ID>::type,
                                            typename C2CVariant<T, N, CONTIG, V>::type>::type;
+};
+
+// The stage whose destination lines step the other way (XS): as above;
+// contiguous-mode kernels take tile variant PFFT_XS_CONTIG_VARIANT.
+#ifndef PFFT_XS_CONTIG_VARIANT
+#define PFFT_XS_CONTIG_VARIANT 1
+#endif
+template <typename T, int N, bool CONTIG>
+struct C2CXsShape {
+    static constexpr int VC = PFFT_XS_CONTIG_VARIANT;
+    static constexpr bool own = CONTIG && C2CVariant<T, N, true, VC>::exists;
+    static constexpr int V = own ? VC : C2CWideShape<T, N, CONTIG>::V;
+    using type = typename std::conditional<own, typename C2CVariant<T, N, true, VC>::type,
+                                           typename C2CWideShape<T, N, CONTIG>::type>::type;
 };
 
 template <typename T, int N, bool CONTIG, int SIGN>
@@ -158,7 +172,7 @@ static hipError_t c2c_launch_xs(const KernelConfig &c, const StageArgs &a, hipSt
 template <typename T, int N, bool CONTIG, int SIGN>
 static hipError_t c2c_launch_wide(const KernelConfig &c, const StageArgs &a, hipStream_t s)
 {
-    using S = typename C2CXsShape<T, N, CONTIG>::type;
+    using S = typename C2CWideShape<T, N, CONTIG>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
     hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S, false, long>), dim3((unsigned)g), dim3(S::NT), 0, s, a,
@@ -274,12 +288,18 @@ static void c2c_cfg_mode(int variant, KernelConfig *c)
         }
         variant = CONTIG ? 1 : (N >= 1024 ? 4 : 3);
     }
-    if (variant == 6 || variant == 7) {  // the shape of the XS stage (6) and of the 64-bit-offset stage (7)
+    if (variant == 6) {  // the shape of the XS stage
         c->W = C2CXsShape<T, N, CONTIG>::type::W;
         c->threads = C2CXsShape<T, N, CONTIG>::type::NT;
         c->id = C2CXsShape<T, N, CONTIG>::V;
-        c->xside = variant == 6;
-        c->wide = variant == 7;
+        c->xside = 1;
+        return;
+    }
+    if (variant == 7) {  // the shape of the 64-bit-offset stage
+        c->W = C2CWideShape<T, N, CONTIG>::type::W;
+        c->threads = C2CWideShape<T, N, CONTIG>::type::NT;
+        c->id = C2CWideShape<T, N, CONTIG>::V;
+        c->wide = 1;
         return;
     }
     if (variant == 1 && C2CVariant<T, N, CONTIG, 1>::exists) {
