@@ -314,7 +314,11 @@ int pfft_adjoint_backward(pfft_plan plan, const void *in, void *out, void *work,
 /*
  * Batches: many plans (any shapes and grids, one precision) executed
  * together.  Launch k of every member that runs the same stage kernel shape
- * becomes one launch over all their tiles, so a batch of n transforms costs
+ * becomes one launch over all their tiles (complex stages of the default
+ * radix plan with 32-bit offsets, and the real-to-complex / complex-to-real
+ * stages; other stages -- real-to-real, copies, XS, 64-bit offsets, the
+ * alternative radix plan, the long-line shapes -- are launched per member
+ * inside the batch), so a batch of n transforms costs
  * about as many kernel launches as one transform of each distinct shape;
  * execution is asynchronous, allocates nothing and can be captured into a
  * HIP graph.  The batch copies what it needs from its plans at creation

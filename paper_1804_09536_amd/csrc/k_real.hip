@@ -28,202 +28,239 @@ struct RealLds {
 // S: the launch shape of the M-point transform (a contiguous-mode C2CCfg).
 // Off: element offsets (long in the plans with buffers of 2^31 elements or more).
 template <typename T, int NR, int KIND, class S, typename Off = int>
-__global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restrict__ tiles)
-{
+struct RealStage {
     using T2 = typename V2<T>::type;
-    constexpr int M = NR / 2;
-    constexpr int P = S::P, TPL = S::TPL, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
+    static constexpr int M = NR / 2;
+    static constexpr int P = S::P, TPL = S::TPL, NL = S::NL, SLOTS = S::SLOTS, W = S::W;
     using LT = LdsTile<T2, M, W, true>;
     using RL = RealLds<T2, M>;
-    constexpr int LDS_N = (LT::SIZE > W * RL::LINE) ? LT::SIZE : W * RL::LINE;
-    __shared__ T2 lds[LDS_N];
-
-    const Tile &t = tiles[blockIdx.x];
-    const int count = t.count;
-    const int tid = threadIdx.x;
-    const int jt = tid % TPL;
-    const int slot = tid / TPL;
-    int wl[NL];
-    bool valid[NL];
-#pragma unroll
-    for (int l = 0; l < NL; l++) {
-        wl[l] = slot + l * SLOTS;
-        valid[l] = wl[l] < count;
-    }
+    static constexpr int LDS_N = (LT::SIZE > W * RL::LINE) ? LT::SIZE : W * RL::LINE;
     // the M-point table and the first M entries of the N-point table, staged
     // in LDS once per workgroup where they are small
-    constexpr bool TW_LDS = TwiddleStage<T2, M>::on;
-    __shared__ T2 twl[TW_LDS ? 2 * M : 1];
-    const T2 *__restrict__ tw = (const T2 *)a.twiddle;    // M-point table
-    const T2 *__restrict__ tw2 = (const T2 *)a.twiddle2;  // N-point table
-    if constexpr (TW_LDS) {
-        for (int i = tid; i < M; i += S::NT) {
-            twl[i] = tw[i];
-            twl[M + i] = tw2[i];
-        }
-        __syncthreads();
-        tw = twl;
-        tw2 = twl + M;
-    }
-    const T scale = (T)a.scale;
-    T2 v[NL][P];
+    static constexpr bool TW_LDS = TwiddleStage<T2, M>::on;
+    static constexpr int TW_N = TW_LDS ? 2 * M : 1;
 
-    if constexpr (KIND == KIND_R2C) {
-        // real side: pairs (2n, 2n+1) of real positions, n = jt + m*TPL
-        SideAddr<P, Off> rs;
-        rs.init(a.side[0], t, 0, 2 * jt, 2 * TPL, NR, true);
-        const T *__restrict__ in = (const T *)a.src;
-        if (count == W) {
-            // whole real lines, each byte read once: streaming loads
-#pragma unroll
-            for (int l = 0; l < NL; l++)
-#pragma unroll
-                for (int m = 0; m < P; m++) v[l][m] = load_stream((const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]));
-        } else {
-#pragma unroll
-            for (int l = 0; l < NL; l++)
-#pragma unroll
-                for (int m = 0; m < P; m++)
-                    v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
+    __device__ static __forceinline__ void stage_twiddles(const StageArgs &a, T2 *twl, const T2 *&tw, const T2 *&tw2)
+    {
+        tw = (const T2 *)a.twiddle;    // M-point table
+        tw2 = (const T2 *)a.twiddle2;  // N-point table
+        if constexpr (TW_LDS) {
+            for (int i = threadIdx.x; i < M; i += S::NT) {
+                twl[i] = tw[i];
+                twl[M + i] = tw2[i];
+            }
+            __syncthreads();
+            tw = twl;
+            tw2 = twl + M;
         }
-        fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
-        __syncthreads();
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++) lds[RL::idx(wl[l], jt + m * TPL)] = v[l][m];
-        __syncthreads();
-        SideAddr<P, Off> cs;
-        cs.init(a.side[1], t, 1, jt, TPL, M + 1, true);
-        T2 *__restrict__ out = (T2 *)a.dst;
-        const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
-        // whole destination lines (the half spectrum stays in its block):
-        // streaming stores
-        const bool stream = a.side[1].R == 0;
+    }
+
+    // One tile of the stage (arguments a, tile t).
+    __device__ static __forceinline__ void run(const StageArgs &a, const Tile &t, T2 *lds, const T2 *__restrict__ tw,
+                                               const T2 *__restrict__ tw2)
+    {
+        const int count = t.count;
+        const int tid = threadIdx.x;
+        const int jt = tid % TPL;
+        const int slot = tid / TPL;
+        int wl[NL];
+        bool valid[NL];
 #pragma unroll
         for (int l = 0; l < NL; l++) {
-            if (!valid[l]) continue;
-#pragma unroll
-            for (int m = 0; m < P; m++) {
-                const int k = jt + m * TPL;
-                const T2 zk = lds[RL::idx(wl[l], k)];
-                T2 zc = lds[RL::idx(wl[l], k == 0 ? 0 : M - k)];
-                zc.y = -zc.y;
-                const T2 e = c_scale(c_add(zk, zc), (T)0.5);
-                T2 d = c_sub(zk, zc);  // (Z_k - conj Z_{M-k})
-                T2 o;                  // -(i/2) d
-                o.x = d.y * (T)0.5;
-                o.y = -d.x * (T)0.5;
-                T2 x = c_add(e, c_mul(tw2[k], o));
-                T f = scale;
-                if (dbl && k > 0) f *= (T)2;
-                T2 *q = out + cs.off[m] + wl[l] * cs.stride[m];
-                if (stream)
-                    store_stream(q, c_scale(x, f));
-                else
-                    *q = c_scale(x, f);
-            }
-            if (jt == 0) {
-                // bin M: E_0 - O_0 = Re Z_0 - Im Z_0
-                const T2 z0 = lds[RL::idx(wl[l], 0)];
-                const Side &sd = a.side[1];
-                const int2 pc = sd.pos[M];
-                const long na = sd.na[pc.x];
-                const long base = sd.rank_off[t.rank[1] + pc.x * sd.R];
-                const long addr = base + ((long)(t.O[1] + wl[l]) * na + pc.y) * t.E[1] + t.I[1];
-                T2 x;
-                x.x = (z0.x - z0.y) * scale;
-                x.y = (T)0;
-                out[addr] = x;
-            }
+            wl[l] = slot + l * SLOTS;
+            valid[l] = wl[l] < count;
         }
-    } else {
-        // complex side: bins k = jt + m*TPL and bin M, through LDS
-        const T2 *__restrict__ in = (const T2 *)a.src;
-        SideAddr<P, Off> cs;
-        cs.init(a.side[0], t, 0, jt, TPL, M + 1, true);
-        const bool half = (a.flags & SF_HALVE_INTERIOR) != 0;
-        // all loads first (a full tile without predicates), then the LDS
-        // writes, so the loads are in flight together
-        if (count == W) {
+        const T scale = (T)a.scale;
+        T2 v[NL][P];
+
+        if constexpr (KIND == KIND_R2C) {
+            // real side: pairs (2n, 2n+1) of real positions, n = jt + m*TPL
+            SideAddr<P, Off> rs;
+            rs.init(a.side[0], t, 0, 2 * jt, 2 * TPL, NR, true);
+            const T *__restrict__ in = (const T *)a.src;
+            if (count == W) {
+                // whole real lines, each byte read once: streaming loads
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++)
+                        v[l][m] = load_stream((const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]));
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++)
+                        v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
+            }
+            fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
+            __syncthreads();
 #pragma unroll
             for (int l = 0; l < NL; l++)
 #pragma unroll
-                for (int m = 0; m < P; m++) v[l][m] = load_stream(in + cs.off[m] + wl[l] * cs.stride[m]);
-        } else {
-#pragma unroll
-            for (int l = 0; l < NL; l++)
-#pragma unroll
-                for (int m = 0; m < P; m++)
-                    v[l][m] = valid[l] ? in[cs.off[m] + wl[l] * cs.stride[m]] : c_zero<T2>();
-        }
-        T2 xm[NL];
-        if (jt == 0) {
-            const Side &sd = a.side[0];
-            const int2 pc = sd.pos[M];
-            const long na = sd.na[pc.x];
-            const long base = sd.rank_off[t.rank[0] + pc.x * sd.R];
+                for (int m = 0; m < P; m++) lds[RL::idx(wl[l], jt + m * TPL)] = v[l][m];
+            __syncthreads();
+            SideAddr<P, Off> cs;
+            cs.init(a.side[1], t, 1, jt, TPL, M + 1, true);
+            T2 *__restrict__ out = (T2 *)a.dst;
+            const bool dbl = (a.flags & SF_DOUBLE_INTERIOR) != 0;
+            // whole destination lines (the half spectrum stays in its block):
+            // streaming stores
+            const bool stream = a.side[1].R == 0;
 #pragma unroll
             for (int l = 0; l < NL; l++) {
-                const long addr = base + ((long)(t.O[0] + wl[l]) * na + pc.y) * t.E[0] + t.I[0];
-                xm[l] = valid[l] ? in[addr] : c_zero<T2>();
+                if (!valid[l]) continue;
+#pragma unroll
+                for (int m = 0; m < P; m++) {
+                    const int k = jt + m * TPL;
+                    const T2 zk = lds[RL::idx(wl[l], k)];
+                    T2 zc = lds[RL::idx(wl[l], k == 0 ? 0 : M - k)];
+                    zc.y = -zc.y;
+                    const T2 e = c_scale(c_add(zk, zc), (T)0.5);
+                    T2 d = c_sub(zk, zc);  // (Z_k - conj Z_{M-k})
+                    T2 o;                  // -(i/2) d
+                    o.x = d.y * (T)0.5;
+                    o.y = -d.x * (T)0.5;
+                    T2 x = c_add(e, c_mul(tw2[k], o));
+                    T f = scale;
+                    if (dbl && k > 0) f *= (T)2;
+                    T2 *q = out + cs.off[m] + wl[l] * cs.stride[m];
+                    if (stream)
+                        store_stream(q, c_scale(x, f));
+                    else
+                        *q = c_scale(x, f);
+                }
+                if (jt == 0) {
+                    // bin M: E_0 - O_0 = Re Z_0 - Im Z_0
+                    const T2 z0 = lds[RL::idx(wl[l], 0)];
+                    const Side &sd = a.side[1];
+                    const int2 pc = sd.pos[M];
+                    const long na = sd.na[pc.x];
+                    const long base = sd.rank_off[t.rank[1] + pc.x * sd.R];
+                    const long addr = base + ((long)(t.O[1] + wl[l]) * na + pc.y) * t.E[1] + t.I[1];
+                    T2 x;
+                    x.x = (z0.x - z0.y) * scale;
+                    x.y = (T)0;
+                    out[addr] = x;
+                }
             }
-        }
-#pragma unroll
-        for (int l = 0; l < NL; l++) {
-#pragma unroll
-            for (int m = 0; m < P; m++) {
-                const int k = jt + m * TPL;
-                T2 x = v[l][m];
-                if (k == 0) x.y = (T)0;
-                if (half && k > 0) x = c_scale(x, (T)0.5);
-                lds[RL::idx(wl[l], k)] = x;
-            }
-            if (jt == 0) {
-                T2 x = xm[l];
-                x.y = (T)0;
-                lds[RL::idx(wl[l], M)] = x;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int l = 0; l < NL; l++)
-#pragma unroll
-            for (int m = 0; m < P; m++) {
-                const int k = jt + m * TPL;
-                const T2 xk = lds[RL::idx(wl[l], k)];
-                T2 xc = lds[RL::idx(wl[l], M - k)];
-                xc.y = -xc.y;
-                const T2 s = c_add(xk, xc);
-                const T2 d = c_sub(xk, xc);
-                T2 w = tw2[k];
-                w.y = -w.y;             // e^{+2 pi i k / N}
-                const T2 wd = c_mul(w, d);
-                T2 z;                   // s + i * wd
-                z.x = s.x - wd.y;
-                z.y = s.y + wd.x;
-                v[l][m] = z;
-            }
-        __syncthreads();
-        fft_passes<T2, M, W, true, 1, NL, 1, 0>(v, wl, jt, lds, tw);
-        SideAddr<P, Off> rs;
-        rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
-        T *__restrict__ out = (T *)a.dst;
-        if (count == W && a.side[1].R == 0) {
-            // whole real lines in the destination: streaming stores
-#pragma unroll
-            for (int l = 0; l < NL; l++)
-#pragma unroll
-                for (int m = 0; m < P; m++)
-                    store_stream((T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]), c_scale(v[l][m], scale));
         } else {
+            // complex side: bins k = jt + m*TPL and bin M, through LDS
+            const T2 *__restrict__ in = (const T2 *)a.src;
+            SideAddr<P, Off> cs;
+            cs.init(a.side[0], t, 0, jt, TPL, M + 1, true);
+            const bool half = (a.flags & SF_HALVE_INTERIOR) != 0;
+            // all loads first (a full tile without predicates), then the LDS
+            // writes, so the loads are in flight together
+            if (count == W) {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++) v[l][m] = load_stream(in + cs.off[m] + wl[l] * cs.stride[m]);
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++)
+                        v[l][m] = valid[l] ? in[cs.off[m] + wl[l] * cs.stride[m]] : c_zero<T2>();
+            }
+            T2 xm[NL];
+            if (jt == 0) {
+                const Side &sd = a.side[0];
+                const int2 pc = sd.pos[M];
+                const long na = sd.na[pc.x];
+                const long base = sd.rank_off[t.rank[0] + pc.x * sd.R];
+#pragma unroll
+                for (int l = 0; l < NL; l++) {
+                    const long addr = base + ((long)(t.O[0] + wl[l]) * na + pc.y) * t.E[0] + t.I[0];
+                    xm[l] = valid[l] ? in[addr] : c_zero<T2>();
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < NL; l++) {
+#pragma unroll
+                for (int m = 0; m < P; m++) {
+                    const int k = jt + m * TPL;
+                    T2 x = v[l][m];
+                    if (k == 0) x.y = (T)0;
+                    if (half && k > 0) x = c_scale(x, (T)0.5);
+                    lds[RL::idx(wl[l], k)] = x;
+                }
+                if (jt == 0) {
+                    T2 x = xm[l];
+                    x.y = (T)0;
+                    lds[RL::idx(wl[l], M)] = x;
+                }
+            }
+            __syncthreads();
 #pragma unroll
             for (int l = 0; l < NL; l++)
 #pragma unroll
-                for (int m = 0; m < P; m++)
-                    if (valid[l]) *(T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]) = c_scale(v[l][m], scale);
+                for (int m = 0; m < P; m++) {
+                    const int k = jt + m * TPL;
+                    const T2 xk = lds[RL::idx(wl[l], k)];
+                    T2 xc = lds[RL::idx(wl[l], M - k)];
+                    xc.y = -xc.y;
+                    const T2 s = c_add(xk, xc);
+                    const T2 d = c_sub(xk, xc);
+                    T2 w = tw2[k];
+                    w.y = -w.y;             // e^{+2 pi i k / N}
+                    const T2 wd = c_mul(w, d);
+                    T2 z;                   // s + i * wd
+                    z.x = s.x - wd.y;
+                    z.y = s.y + wd.x;
+                    v[l][m] = z;
+                }
+            __syncthreads();
+            fft_passes<T2, M, W, true, 1, NL, 1, 0>(v, wl, jt, lds, tw);
+            SideAddr<P, Off> rs;
+            rs.init(a.side[1], t, 1, 2 * jt, 2 * TPL, NR, true);
+            T *__restrict__ out = (T *)a.dst;
+            if (count == W && a.side[1].R == 0) {
+                // whole real lines in the destination: streaming stores
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++)
+                        store_stream((T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]), c_scale(v[l][m], scale));
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; l++)
+#pragma unroll
+                    for (int m = 0; m < P; m++)
+                        if (valid[l]) *(T2 *)(out + rs.off[m] + wl[l] * rs.stride[m]) = c_scale(v[l][m], scale);
+            }
         }
     }
+};
+
+template <typename T, int NR, int KIND, class S, typename Off = int>
+__global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restrict__ tiles)
+{
+    using R = RealStage<T, NR, KIND, S, Off>;
+    using T2 = typename R::T2;
+    __shared__ T2 lds[R::LDS_N];
+    __shared__ T2 twl[R::TW_N];
+    const T2 *tw, *tw2;
+    R::stage_twiddles(a, twl, tw, tw2);
+    R::run(a, tiles[blockIdx.x], lds, tw, tw2);
+}
+
+// The same stage over the tiles of several transforms in one launch (a
+// batch): each tile carries the index of its transform's arguments in bits
+// 8..31 of its flags; the members share the length, so the twiddle tables of
+// the first member serve all.
+template <typename T, int NR, int KIND, class S>
+__global__ __launch_bounds__(S::NT) void k_real_multi(const StageArgs *__restrict__ args,
+                                                      const Tile *__restrict__ tiles)
+{
+    using R = RealStage<T, NR, KIND, S, int>;
+    using T2 = typename R::T2;
+    __shared__ T2 lds[R::LDS_N];
+    __shared__ T2 twl[R::TW_N];
+    const T2 *tw, *tw2;
+    R::stage_twiddles(args[0], twl, tw, tw2);
+    const Tile &t = tiles[blockIdx.x];
+    R::run(args[t.flags >> 8], t, lds, tw, tw2);
 }
 
 #define PFFT_FOR_EACH_NR(X)                                                                             \
@@ -282,6 +319,35 @@ static hipError_t real_launch_v(int kind, const StageArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int NR, int V>
+static hipError_t real_launch_multi_v(int kind, const StageArgs *args, const Tile *tiles, long nt, hipStream_t s)
+{
+    using S = typename RealShape<T, NR>::template type<V>;
+    dim3 grid((unsigned)(nt < 1 ? 1 : nt));
+    if (kind == KIND_R2C)
+        hipLaunchKernelGGL((k_real_multi<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, args, tiles);
+    else
+        hipLaunchKernelGGL((k_real_multi<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, args, tiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t real_launch_multi_t(int NR, int kind, int variant, const StageArgs *args, const Tile *tiles, long nt,
+                                      hipStream_t s)
+{
+    switch (NR) {
+#define PFFT_CASE(n)                                                                               \
+    case n:                                                                                        \
+        return variant == 1   ? real_launch_multi_v<T, n, 1>(kind, args, tiles, nt, s)            \
+               : variant == 2 ? real_launch_multi_v<T, n, 2>(kind, args, tiles, nt, s)            \
+                              : real_launch_multi_v<T, n, 0>(kind, args, tiles, nt, s);
+        PFFT_FOR_EACH_NR(PFFT_CASE)
+#undef PFFT_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 static hipError_t real_launch_t(int NR, int kind, int variant, int wide, const StageArgs &a, hipStream_t s)
 {
@@ -303,6 +369,13 @@ int real_config(int prec, int N, int kind, int variant, KernelConfig *cfg)
 {
     (void)kind;
     return prec == 0 ? real_config_t<float>(N, variant, cfg) : real_config_t<double>(N, variant, cfg);
+}
+
+hipError_t real_launch_multi(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs *args,
+                             const Tile *tiles, long nt, hipStream_t s)
+{
+    return prec == 0 ? real_launch_multi_t<float>(N, kind, cfg.id, args, tiles, nt, s)
+                     : real_launch_multi_t<double>(N, kind, cfg.id, args, tiles, nt, s);
 }
 
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s)

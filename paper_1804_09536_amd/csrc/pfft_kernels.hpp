@@ -53,6 +53,9 @@ int mixed_bluestein_length(int N);
 int mixed_config(int prec, int N, int kind, KernelConfig *cfg);
 hipError_t mixed_launch(int prec, int kind, int sign, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
 hipError_t real_launch(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);
+// the same over the tiles of several transforms (member index in bits 8..31 of the tile flags)
+hipError_t real_launch_multi(int prec, int N, int kind, const KernelConfig &cfg, const StageArgs *args,
+                             const Tile *tiles, long nt, hipStream_t s);
 int r2r_config_f32(int N, int contig, int variant, KernelConfig *cfg);
 int r2r_config_f64(int N, int contig, int variant, KernelConfig *cfg);
 hipError_t r2r_launch_f32(int N, int contig, const KernelConfig &cfg, const StageArgs &a, hipStream_t s);

@@ -1405,6 +1405,15 @@ static int validate_launch(const pfft_plan_s *p, const Launch &ln, const char *w
 // sides stepping alike, 32-bit offsets, a register plan for the length).
 static bool multi_kernel(const KernelConfig &c) { return c.id >= 0 && c.id <= 4 && !c.xside && !c.alt && !c.wide; }
 
+// Stages of a batch that run as one launch over the tiles of all members of
+// a group: complex stages with a multi-transform kernel, and real-to-complex
+// / complex-to-real stages with 32-bit offsets.
+static bool batch_multi(int kind, const KernelConfig &c)
+{
+    if (kind == KIND_C2C) return multi_kernel(c);
+    return (kind == KIND_R2C || kind == KIND_C2R) && !c.wide && c.id >= 0 && c.id <= 2;
+}
+
 struct BatchGroup {
     int k = 0;              // launch index within each member's list
     int kind = KIND_C2C;
@@ -1484,10 +1493,10 @@ static int batch_plan(pfft_batch_s *b)
                 const Launch &ln = list[k];
                 BatchGroup *g = nullptr;
                 // a multi-transform kernel exists (not for stages whose sides step differently)
-                const bool multi = ln.kind == KIND_C2C && multi_kernel(ln.cfg);
+                const bool multi = batch_multi(ln.kind, ln.cfg);
                 if (multi)
                     for (auto &x : gs)
-                        if (x.kind == KIND_C2C && multi_kernel(x.cfg) && x.N == ln.N && x.contig == ln.contig &&
+                        if (x.kind == ln.kind && batch_multi(x.kind, x.cfg) && x.N == ln.N && x.contig == ln.contig &&
                             x.cfg.id == ln.cfg.id && x.cfg.resident == ln.cfg.resident)
                             g = &x;
                 if (!g) {
@@ -1502,7 +1511,7 @@ static int batch_plan(pfft_batch_s *b)
                 g->members.push_back(m);
             }
             for (auto &g : gs) {
-                if (g.kind == KIND_C2C && multi_kernel(g.cfg)) {
+                if (batch_multi(g.kind, g.cfg)) {
                     int64_t nt = 0;
                     for (int m : g.members) nt += (dir == 0 ? b->plans[m]->fwd : b->plans[m]->bwd)[k].ntiles;
                     if ((int64_t)g.members.size() >= (1 << 23)) return fail(PFFT_EINVAL, "too many batch members");
@@ -1534,7 +1543,7 @@ static void batch_fill_args(pfft_batch_s *b)
     const uint8_t *dev = (const uint8_t *)b->dev;
     for (int dir = 0; dir < 2; dir++) {
         for (auto &g : b->groups[dir]) {
-            if (g.kind != KIND_C2C || !multi_kernel(g.cfg)) continue;
+            if (!batch_multi(g.kind, g.cfg)) continue;
             StageArgs *args = (StageArgs *)(b->blob.data() + g.off_args);
             for (size_t mi = 0; mi < g.members.size(); mi++) {
                 const int m = g.members[mi];
@@ -2042,11 +2051,13 @@ int pfft_batch_execute(pfft_batch b, int direction, hipStream_t stream)
     const uint8_t *dev = (const uint8_t *)b->dev;
     const int sign = direction == 0 ? -1 : 1;
     for (const auto &g : b->groups[direction]) {
-        if (g.kind == KIND_C2C && multi_kernel(g.cfg)) {
+        if (batch_multi(g.kind, g.cfg)) {
             if (g.ntiles == 0) continue;
             const StageArgs *args = (const StageArgs *)(dev + g.off_args);
             const Tile *tiles = (const Tile *)(dev + g.off_tiles);
             hipError_t e = launch_fault_injected() ? hipErrorLaunchFailure
+                           : g.kind != KIND_C2C
+                               ? real_launch_multi(b->precision, g.N, g.kind, g.cfg, args, tiles, g.ntiles, stream)
                            : b->precision == PFFT_F32
                                ? c2c_launch_multi_f32(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream)
                                : c2c_launch_multi_f64(g.N, g.contig, sign, g.cfg, args, tiles, g.ntiles, stream);

@@ -17,7 +17,7 @@ MEMBERS = [
     ((24, 12, 48), (2, 2), "c2c"),       # radix-3 lengths
     ((32, 32, 32), (4,), "c2c"),         # slab
     ((8, 16, 4, 32), (3, 1, 5), "c2c"),  # 4-D
-    ((16, 16, 32), (4, 2), "r2c"),       # real input (per-member launches inside the batch)
+    ((16, 16, 32), (4, 2), "r2c"),       # real input (its r2c/c2r stages run the multi-transform kernel)
     ((12, 16, 24), (2, 3), "r2r"),       # cosine/sine transforms (per-member launches)
 ]
 R2R = ("dst2", "dct2", "dst2")
@@ -151,3 +151,41 @@ def test_config5_batch_matches_oracle(config5_batch, sid):
         assert np.linalg.norm(outs[m] - expect) / np.linalg.norm(expect) <= 1e-5, (shape, c)
         expect_b = oracle.backward(ch, outs[m].astype(np.complex128))
         assert np.linalg.norm(backs[m] - expect_b) / np.linalg.norm(expect_b) <= 1e-5, (shape, c)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_real_members_share_launches(prec):
+    # real-input members of one line length (and of two shapes of tile) in
+    # one batch: the grouped r2c / c2r launches give each member's own
+    # results bit for bit, and the oracle's
+    specs = [((16, 16, 32), (4, 2)), ((8, 24, 32), (2, 3)), ((32, 8, 32), (2, 2)), ((16, 16, 32), (4, 2)),
+             ((12, 10, 96), (3, 2))]
+    plans = [Plan(s, g, kind="r2c", precision=prec) for s, g in specs]
+    b = Batch(plans)
+    rdt = np.float32 if prec == "f32" else np.float64
+    data = []
+    for m, p in enumerate(b.plans):
+        u = inputs.gaussian_real(b.inputs[m].numel(), [31, m], rdt)
+        b.inputs[m].copy_(torch.from_numpy(u))
+        data.append(u)
+    b.forward()
+    torch.cuda.synchronize()
+    outs = []
+    for m, p in enumerate(b.plans):
+        print("member", m, p.shape, p.grid, flush=True)
+        ref = p.forward(torch.from_numpy(data[m]).cuda())
+        torch.cuda.synchronize()
+        got = b.outputs[m].cpu().numpy()
+        assert got.tobytes() == ref.cpu().numpy().tobytes()
+        ch = oracle.Chain.paper(p.shape, p.grid, kind="r2c")
+        expect = oracle.forward(ch, data[m].astype(np.float64))
+        assert np.linalg.norm(got - expect) / np.linalg.norm(expect) <= (1e-5 if prec == "f32" else 1e-12)
+        outs.append(got)
+    b.backward()
+    torch.cuda.synchronize()
+    for m, p in enumerate(b.plans):
+        ref = p.backward(torch.from_numpy(outs[m]).cuda())
+        torch.cuda.synchronize()
+        assert b.inputs[m].cpu().numpy().tobytes() == ref.cpu().numpy().tobytes()
+        assert np.linalg.norm(b.inputs[m].cpu().numpy() - data[m]) / np.linalg.norm(data[m]) <= \
+            (1e-5 if prec == "f32" else 1e-12)
