@@ -319,7 +319,10 @@ def measure_plain(name, steps, warmup, path="fused", placement=None, profile=Tru
             u_np = inputs.gaussian_real(n_in, [2], np.float32 if prec == "f32" else np.float64)
         x = torch.from_numpy(u_np).to(dev)
     y = plan.empty(plan.num_layouts - 1)
-    z = plan.empty(0, real=(kind == "r2c"))
+    # buffers beyond 32 GiB (2048^3 complex64: 64 GiB each): the backward
+    # writes into the input buffer, so three buffers fit one device
+    huge = x.numel() * x.element_size() > (32 << 30)
+    z = x if huge else plan.empty(0, real=(kind == "r2c"))
     work = plan.workspace()
 
     def step():
@@ -364,11 +367,12 @@ def measure_plain(name, steps, warmup, path="fused", placement=None, profile=Tru
                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
                     "traffic": measured_traffic(dom) if traffic else None,
                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": per_launch}
-    # round-trip sanity on the last step
-    rt = float(torch.linalg.vector_norm((z - x).flatten()) / torch.linalg.vector_norm(x.flatten()))
+    # round-trip sanity on the last step (not for the huge buffers, whose
+    # input is overwritten; the tests check those against closed forms)
+    rt = None if huge else float(torch.linalg.vector_norm((z - x).flatten()) / torch.linalg.vector_norm(x.flatten()))
     return {"plan": plan, "step": step, "x": x, "y": y, "u_np": u_np, "shape": shape, "grid": grid, "kind": kind,
             "prec": prec, "chain": chain, "ms": ms_per_step, "step_bytes": step_bytes, "per_kernel": per_kernel,
-            "roofline": roofline, "roundtrip": rt}
+            "roofline": roofline, "roundtrip": rt, "huge": huge}
 
 
 def plain_record(name, steps, warmup):
@@ -426,7 +430,7 @@ def main():
     # The paper's statistic (outside the timed region, Sec. 4): 50 blocks of 3
     # uninterrupted forward+backward pairs, each block bracketed by events on
     # the stream; the fastest block (and the median) divided by 3.
-    outer, inner = 50, 3
+    outer, inner = (10 if r["huge"] else 50), 3
     blocks = []
     for _ in range(outer):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -442,7 +446,8 @@ def main():
 
     # Copy ceiling: a device-to-device copy of one buffer of the workload's
     # size (read + write), the practical bound of any pass over the array.
-    src_c, dst_c = y, torch.empty_like(y)
+    src_c = y[: 1 << 27] if r["huge"] else y  # (a 1 GiB piece of the huge buffers)
+    dst_c = torch.empty_like(src_c)
     for _ in range(2):
         dst_c.copy_(src_c)
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -452,9 +457,9 @@ def main():
     c1.record()
     c1.synchronize()
     copy_ms = c0.elapsed_time(c1) / 10
-    copy_gbps = 2 * y.numel() * y.element_size() / (copy_ms * 1e-3) / 1e9
+    copy_gbps = 2 * src_c.numel() * src_c.element_size() / (copy_ms * 1e-3) / 1e9
     del dst_c
-    copy_probe = {"bytes": 2 * y.numel() * y.element_size(), "ms": round(copy_ms, 4), "gbps": round(copy_gbps, 1),
+    copy_probe = {"bytes": 2 * src_c.numel() * src_c.element_size(), "ms": round(copy_ms, 4), "gbps": round(copy_gbps, 1),
                   "dominant_kernel_frac_of_copy": round(roofline["achieved"] / copy_gbps, 4) if roofline else None}
 
     if args.copy_calibration:
