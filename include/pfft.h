@@ -227,6 +227,10 @@ typedef struct {
                            rounding.  Stages with 64-bit offsets or differently stepping sides, and
                            other lengths, keep their kernels; such stages leave the multi-transform
                            kernel of batches. */
+    int stream_contig;  /* complex contiguous stages: 0 ordinary loads and stores, 1 streaming loads,
+                           2 streaming stores (of whole destination lines), 3 both, 4 by the plan's
+                           rule (the default): both where source and destination together exceed
+                           256 MiB (the last-level cache), else streaming loads only */
 } pfft_tuning;
 
 int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *tuning);

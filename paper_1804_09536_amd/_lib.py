@@ -31,7 +31,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile_contig", ctypes.c_int), ("tile_strided", ctypes.c_int),
                 ("resident_contig", ctypes.c_int), ("resident_strided", ctypes.c_int),
                 ("xcd_order", ctypes.c_int), ("stream_strided", ctypes.c_int), ("wide_offsets", ctypes.c_int),
-                ("radix_alt", ctypes.c_int)]
+                ("radix_alt", ctypes.c_int), ("stream_contig", ctypes.c_int)]
 
 
 class ProfileEntry(ctypes.Structure):

@@ -165,11 +165,17 @@ struct C2CWorker {
         int lo[NL];
         if constexpr (!CONTIG) line_offsets(t, 0, lo);
         if (fast && CONTIG) {
-            // lines along the last axis (whole, or gathered in pieces): streaming loads
+            // lines along the last axis (whole, or gathered in pieces):
+            // streaming loads where the stage asks for them (always in the
+            // multi-transform kernel)
+            const bool nt = !STREAM || (a.flags & SF_LOAD_NT) != 0;
 #pragma unroll
             for (int l = 0; l < NL; l++)
 #pragma unroll
-                for (int m = 0; m < P; m++) v[l][m] = load_stream(in + src.off[m] + wl[l] * src.stride[m]);
+                for (int m = 0; m < P; m++) {
+                    const T2 *p2 = in + src.off[m] + wl[l] * src.stride[m];
+                    v[l][m] = nt ? load_stream(p2) : *p2;
+                }
         } else if (fast) {
             // rows of adjacent lines; streaming loads where the stage asks for them
             const bool nt = STREAM && (a.flags & SF_LOAD_NT) != 0;
@@ -297,9 +303,10 @@ struct C2CWorker {
             return;
         }
         // Whole destination lines along the last axis are written with
-        // streaming stores (measured faster); rows of strided tiles and line
-        // segments scattered over several blocks with ordinary stores.
-        const bool stream = CONTIG && a.side[1].R == 0;
+        // streaming stores where the stage asks for them (always in the
+        // multi-transform kernel); rows of strided tiles and line segments
+        // scattered over several blocks with ordinary stores.
+        const bool stream = CONTIG && a.side[1].R == 0 && (!STREAM || (a.flags & SF_STORE_NT) != 0);
         int lo[NL];
         if constexpr (!CONTIG) line_offsets(t, 1, lo);
         if (count > 0 && stream) {

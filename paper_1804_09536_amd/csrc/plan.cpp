@@ -757,6 +757,16 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
         const int rule = bytes > 256.0 * 1048576.0 ? (ln.xcd ? 1 : 3) : 0;
         ln.stream = tu.stream_strided == 4 ? rule : tu.stream_strided;
     }
+    // Contiguous stages: streaming loads always; streaming stores of whole
+    // destination lines only where source and destination exceed the
+    // last-level cache (the next stage reads a smaller output from there:
+    // 64^4 0.475 -> 0.464 ms, 256^3 0.369 -> 0.363, 128x256x512 0.377 -> 0.373).
+    if (ln.kind == KIND_C2C && ln.contig) {
+        const double esz = p->precision == PFFT_F32 ? 8.0 : 16.0;
+        const double bytes = ((double)p->layouts[ln.src].total() + (double)p->layouts[ln.dst].total()) * esz;
+        const int rule = bytes > 256.0 * 1048576.0 ? 3 : 1;
+        ln.stream = tu.stream_contig == 4 ? rule : tu.stream_contig;
+    }
     return PFFT_OK;
 }
 
@@ -1010,6 +1020,7 @@ static pfft_tuning default_tuning()
     t.stream_strided = 4;
     t.wide_offsets = 0;
     t.radix_alt = 0;
+    t.stream_contig = 4;
     return t;
 }
 
@@ -1669,7 +1680,8 @@ int pfft_plan_set_tuning(pfft_plan plan, const pfft_tuning *t)
     if (t->tile_contig < 0 || t->tile_contig > 5 || t->tile_strided < 0 || t->tile_strided > 7 ||
         t->resident_contig < 0 || t->resident_contig > 1 || t->resident_strided < 0 || t->resident_strided > 1 ||
         t->xcd_order < 0 || t->xcd_order > 2 || t->stream_strided < 0 || t->stream_strided > 4 || t->wide_offsets < 0 ||
-        t->wide_offsets > 1 || t->radix_alt < 0 || t->radix_alt > 3)
+        t->wide_offsets > 1 || t->radix_alt < 0 || t->radix_alt > 3 ||
+        t->stream_contig < 0 || t->stream_contig > 4)
         return fail(PFFT_EINVAL, "tuning field out of range");
     // rebuild every table with the new kernel shapes; the device state must be bound again
     plan->tuning = *t;

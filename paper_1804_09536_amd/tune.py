@@ -25,7 +25,8 @@ TILES = {"tile_strided": (0, 1, 2, 3, 4, 5, 6, 7), "tile_contig": (0, 1, 2, 3, 4
 RESIDENT = (0, 1)
 PLACEMENTS = ("gather", "scatter", "direct", "final")
 # single knobs searched one at a time after the tile shapes
-KNOBS = (("xcd_order", (0, 1, 2)), ("stream_strided", (0, 1, 2, 3, 4)), ("radix_alt", (0, 1, 2, 3)))
+KNOBS = (("xcd_order", (0, 1, 2)), ("stream_strided", (0, 1, 2, 3, 4)), ("stream_contig", (0, 1, 2, 3, 4)),
+         ("radix_alt", (0, 1, 2, 3)))
 
 
 # Choices measured on MI355X for the workloads of the bench (written by

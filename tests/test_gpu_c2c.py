@@ -231,6 +231,12 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
             assert got.tobytes() == ref.tobytes(), (placement, tc, ts, rc, rs, xo, sm)
             back = _host(p.backward(_to_dev(ref)))
             assert back.tobytes() == ref_b.tobytes(), (placement, tc, ts, rc, rs, xo, sm)
+        # streaming modes of the contiguous stages, with the default tiles
+        p.set_tuning(**d)
+        for sc in range(5):
+            p.set_tuning(stream_contig=sc)
+            assert _host(p.forward(x)).tobytes() == ref.tobytes(), (placement, sc)
+            assert _host(p.backward(_to_dev(ref))).tobytes() == ref_b.tobytes(), (placement, sc)
 
 
 @pytest.mark.parametrize("shape,grid,kind,placement,path", [
