@@ -6,6 +6,12 @@
 
 namespace pfft {
 
+LaunchEvents &launch_events()
+{
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 int resident_workgroups(const void *kernel, int nt)
 {
     int dev = 0, cus = 0, per_cu = 0;

@@ -54,7 +54,7 @@ static hipError_t c2c_launch_v(const KernelConfig &c, const StageArgs &a, hipStr
         if (g > resident) g = resident;
     }
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -100,7 +100,7 @@ static hipError_t c2c_launch_slot(const KernelConfig &c, const StageArgs &a, hip
     using S = typename C2CSlot<T, N, ID>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
-    hipLaunchKernelGGL((k_c2c<T, N, false, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_c2c<T, N, false, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -126,7 +126,7 @@ static hipError_t c2c_launch_alt(const KernelConfig &c, const StageArgs &a, hipS
     using S = typename C2CAlt<T, N, CONTIG>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
-    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_c2c<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -163,7 +163,7 @@ static hipError_t c2c_launch_xs(const KernelConfig &c, const StageArgs &a, hipSt
     using S = typename C2CXsShape<T, N, CONTIG>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
-    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S, true>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_c2c<T, N, CONTIG, SIGN, S, true>), dim3((unsigned)g), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -175,7 +175,7 @@ static hipError_t c2c_launch_wide(const KernelConfig &c, const StageArgs &a, hip
     using S = typename C2CWideShape<T, N, CONTIG>::type;
     (void)c;
     long g = a.ntiles < 1 ? 1 : a.ntiles;
-    hipLaunchKernelGGL((k_c2c<T, N, CONTIG, SIGN, S, false, long>), dim3((unsigned)g), dim3(S::NT), 0, s, a,
+    PFFT_LAUNCH((k_c2c<T, N, CONTIG, SIGN, S, false, long>), dim3((unsigned)g), dim3(S::NT), 0, s, a,
                        a.tiles);
     return hipGetLastError();
 }
@@ -192,7 +192,7 @@ static hipError_t c2c_launch_multi_v(const KernelConfig &c, const StageArgs *arg
         if (g > resident) g = resident;
     }
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_c2c_multi<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, args, tiles, nt);
+    PFFT_LAUNCH((k_c2c_multi<T, N, CONTIG, SIGN, S>), dim3((unsigned)g), dim3(S::NT), 0, s, args, tiles, nt);
     return hipGetLastError();
 }
 

@@ -76,12 +76,12 @@ hipError_t copy_launch(size_t esize, const KernelConfig &cfg, const StageArgs &a
     // 64-bit offsets in plans with buffers of 2^31 elements or more
     const long key = (long)esize * (cfg.wide ? -1 : 1);
     switch (key) {
-    case 4: hipLaunchKernelGGL((k_copy<float, int>), grid, block, 0, s, a, cfg.id); break;
-    case 8: hipLaunchKernelGGL((k_copy<float2, int>), grid, block, 0, s, a, cfg.id); break;
-    case 16: hipLaunchKernelGGL((k_copy<double2, int>), grid, block, 0, s, a, cfg.id); break;
-    case -4: hipLaunchKernelGGL((k_copy<float, long>), grid, block, 0, s, a, cfg.id); break;
-    case -8: hipLaunchKernelGGL((k_copy<float2, long>), grid, block, 0, s, a, cfg.id); break;
-    case -16: hipLaunchKernelGGL((k_copy<double2, long>), grid, block, 0, s, a, cfg.id); break;
+    case 4: PFFT_LAUNCH((k_copy<float, int>), grid, block, 0, s, a, cfg.id); break;
+    case 8: PFFT_LAUNCH((k_copy<float2, int>), grid, block, 0, s, a, cfg.id); break;
+    case 16: PFFT_LAUNCH((k_copy<double2, int>), grid, block, 0, s, a, cfg.id); break;
+    case -4: PFFT_LAUNCH((k_copy<float, long>), grid, block, 0, s, a, cfg.id); break;
+    case -8: PFFT_LAUNCH((k_copy<float2, long>), grid, block, 0, s, a, cfg.id); break;
+    case -16: PFFT_LAUNCH((k_copy<double2, long>), grid, block, 0, s, a, cfg.id); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

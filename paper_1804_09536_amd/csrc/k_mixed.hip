@@ -393,7 +393,7 @@ hipError_t mixed_launch(int prec, int kind, int sign, const KernelConfig &cfg, c
     const size_t lds = mixed_lds(prec, a.M > 0 ? a.M : a.N, cfg.W);
     if (lds > 64 * 1024 && mixed_prepare() != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.ntiles), block(kMixedThreads);
-#define PFFT_MIXED(T, K) hipLaunchKernelGGL((k_mixed<T, K>), grid, block, lds, s, a, a.tiles, sign, cfg.W)
+#define PFFT_MIXED(T, K) PFFT_LAUNCH((k_mixed<T, K>), grid, block, lds, s, a, a.tiles, sign, cfg.W)
     if (prec == 0) {
         if (kind == KIND_C2C) PFFT_MIXED(float, KIND_C2C);
         else if (kind == KIND_R2C) PFFT_MIXED(float, KIND_R2C);

@@ -567,7 +567,7 @@ template <typename T, int N, bool CONTIG, int V>
 static hipError_t r2r_launch_full(const StageArgs &a, hipStream_t s)
 {
     using S = R2RCfg<T, N, CONTIG, V>;
-    hipLaunchKernelGGL((k_r2r<T, N, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_r2r<T, N, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -575,7 +575,7 @@ template <typename T, int M, bool CONTIG, int V>
 static hipError_t r2r_launch_half(const StageArgs &a, hipStream_t s)
 {
     using S = R2RCfg<T, M, CONTIG, V>;
-    hipLaunchKernelGGL((k_r2r_half<T, M, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
+    PFFT_LAUNCH((k_r2r_half<T, M, CONTIG, S>), dim3((unsigned)a.ntiles), dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 

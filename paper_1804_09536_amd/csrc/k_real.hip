@@ -313,9 +313,9 @@ static hipError_t real_launch_v(int kind, const StageArgs &a, hipStream_t s)
     using S = typename RealShape<T, NR>::template type<V>;
     dim3 grid((unsigned)a.ntiles);
     if (kind == KIND_R2C)
-        hipLaunchKernelGGL((k_real<T, NR, KIND_R2C, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
+        PFFT_LAUNCH((k_real<T, NR, KIND_R2C, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
     else
-        hipLaunchKernelGGL((k_real<T, NR, KIND_C2R, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
+        PFFT_LAUNCH((k_real<T, NR, KIND_C2R, S, Off>), grid, dim3(S::NT), 0, s, a, a.tiles);
     return hipGetLastError();
 }
 
@@ -325,9 +325,9 @@ static hipError_t real_launch_multi_v(int kind, const StageArgs *args, const Til
     using S = typename RealShape<T, NR>::template type<V>;
     dim3 grid((unsigned)(nt < 1 ? 1 : nt));
     if (kind == KIND_R2C)
-        hipLaunchKernelGGL((k_real_multi<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, args, tiles);
+        PFFT_LAUNCH((k_real_multi<T, NR, KIND_R2C, S>), grid, dim3(S::NT), 0, s, args, tiles);
     else
-        hipLaunchKernelGGL((k_real_multi<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, args, tiles);
+        PFFT_LAUNCH((k_real_multi<T, NR, KIND_C2R, S>), grid, dim3(S::NT), 0, s, args, tiles);
     return hipGetLastError();
 }
 

@@ -2,12 +2,32 @@
 // HIP kernels of libpfft.  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
 #include "pfft_internal.hpp"
 
 namespace pfft {
+
+// Timing events of the next stage launch on this thread (both null: none).
+// With them the launch goes through hipExtLaunchKernelGGL, which stamps the
+// kernel's own start and end into the events: per-launch timing without
+// event packets between the kernels.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+LaunchEvents &launch_events();
+
+#define PFFT_LAUNCH(kernel, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                                  \
+        const ::pfft::LaunchEvents &ev_ = ::pfft::launch_events();                                      \
+        if (ev_.start)                                                                                    \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+        else                                                                                              \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                          \
+    } while (0)
 
 // Launch shape of a stage kernel: at most W lines per tile, `threads` per
 // workgroup; `id` selects a variant in the dispatch tables.

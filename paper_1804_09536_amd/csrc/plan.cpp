@@ -1119,21 +1119,20 @@ static int run_launch(pfft_plan_s *p, const Launch &ln, const void *src, void *d
     if (ln.ntiles == 0) return PFFT_OK;
     hipEvent_t ea = nullptr, eb = nullptr;
     if (p->profiling) {
+        // the kernel's own start and end (every stage is one kernel launch)
         ea = pool_event(p);
         eb = pool_event(p);
         if (!ea || !eb) return fail(PFFT_EHIP, "hipEventCreate failed");
-        if (hipEventRecord(ea, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
     }
     flags = stage_flags(ln, sign, flags);
     const StageArgs a = stage_args(p, ln, (const uint8_t *)p->dev, src, dst, scale, flags);
+    launch_events() = LaunchEvents{ea, eb};
     int rc = launch_fault_injected()
                  ? (int)hipErrorLaunchFailure
                  : launch_stage(ln.kind, p->precision, ln.N, ln.contig, sign, ln.cfg, launch_esize(p, ln), a, stream);
+    launch_events() = LaunchEvents{};
     if (rc != 0) return fail(PFFT_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
-    if (p->profiling) {
-        if (hipEventRecord(eb, stream) != hipSuccess) return fail(PFFT_EHIP, "hipEventRecord failed");
-        p->prof.push_back({ln.kind, ln.axis, ln.contig, ln.N, direction, launch_bytes(p, ln), ea, eb});
-    }
+    if (p->profiling) p->prof.push_back({ln.kind, ln.axis, ln.contig, ln.N, direction, launch_bytes(p, ln), ea, eb});
     return PFFT_OK;
 }
 
