@@ -261,7 +261,8 @@ def bench_grad(steps, warmup):
 
     dev = torch.device("cuda:0")
     shape, grid = (256, 256, 256), (4, 4)
-    plan = Plan(shape, grid, kind="r2c", device=dev).bind()
+    from paper_1804_09536_amd import tune
+    plan = tune.tuned_plan(shape, grid, kind="r2c", tune_missing=False, device=dev).bind()
     w = pad.wavenumber_weight(plan).to(torch.float32)
     u0 = torch.from_numpy(inputs.gaussian_real(plan.buffer_numel(0, real=True), [5], np.float32)).to(dev)
     u = u0.clone().requires_grad_()
@@ -303,9 +304,17 @@ def measure_plain(name, steps, warmup, path="fused", placement=None, profile=Tru
 
     shape, grid, kind, prec, chain = WORKLOADS[name][:5]
     extra = WORKLOADS[name][5] if len(WORKLOADS[name]) > 5 else {}
+    from paper_1804_09536_amd import tune
+
     dev = torch.device("cuda:0")
-    plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=path, device=dev,
-                placement=placement, **extra).bind()
+    if placement is None and not extra:
+        # the autotuner's choice for this workload on this device where it
+        # has one (the user cache, else the shipped table), else the defaults
+        plan = tune.tuned_plan(shape, grid, kind=kind, precision=prec, chain=chain, path=path, tune_missing=False,
+                               device=dev).bind()
+    else:
+        plan = Plan(shape, grid, precision=prec, kind=kind, chain=chain, path=path, device=dev,
+                    placement=placement, **extra).bind()
     n_in = plan.buffer_numel(0, real=(kind == "r2c"))
     # arrays beyond 2^28 elements are drawn on the device (no host copy, no CPU baseline)
     big = n_in > (1 << 28)
@@ -388,7 +397,8 @@ def plain_record(name, steps, warmup):
            "ms_per_step": round(r["ms"], 4), "step_bytes": r["step_bytes"],
            "pct_hbm_peak": round(100.0 * r["step_bytes"] / (r["ms"] * 1e-3) / HBM_PEAK, 2),
            "per_kernel_avg_ms": {k: round(v["ms"] / v["n"], 4) for k, v in r["per_kernel"].items()},
-           "roofline": r["roofline"], "roundtrip_rel_l2": r["roundtrip"]}
+           "roofline": r["roofline"], "roundtrip_rel_l2": r["roundtrip"],
+           "placement": list(r["plan"].placement), "autotuned": bool(getattr(r["plan"], "tuned", False))}
     del r
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -488,7 +498,8 @@ def main():
                                   else ("complex64" if prec == "f32" else "complex128"),
                                   "x".join(map(str, grid)), args.path),
                    "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path,
-                   "placement": list(plan.placement), "tuning": plan.tuning()},
+                   "placement": list(plan.placement), "tuning": plan.tuning(),
+                   "autotuned": bool(getattr(plan, "tuned", False))},
         "step_bytes": step_bytes,
         "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
         "roundtrip_rel_l2": r["roundtrip"],
