@@ -30,7 +30,8 @@ KNOBS = (("xcd_order", (0, 1, 2)), ("stream_strided", (0, 1, 2, 3, 4)), ("stream
 
 
 # Choices measured on MI355X for the workloads of the bench (written by
-# `python -m paper_1804_09536_amd.tune --out <this file> --case ...`), used
+# `python -m paper_1804_09536_amd.tune --out <this file> --case ...`, each
+# kept where the bench measured it faster than the library defaults), used
 # where the user cache has no entry.
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
