@@ -36,6 +36,9 @@ CASES = [
     ((24, 16, 32), (4,), "r2c", "f32", None),
     ((24, 16, 32), (2, 4), "r2c", "f64", ("scatter", "gather")),
     ((128, 128, 128), (4, 4), "c2c", "f32", None),
+    ((96, 48, 40), (4, 2), "c2c", "f32", None),      # 3*2^a lines into the transposed layout
+    ((384, 24, 20), (2, 2), "c2c", "f64", None),
+    ((2048, 6, 16), (2, 2), "c2c", "f32", None),     # long lines: slot-group shapes (stores point by point)
 ]
 
 
