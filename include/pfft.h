@@ -361,9 +361,10 @@ int pfft_batch_execute(pfft_batch batch, int direction, hipStream_t stream);
 int pfft_validate_plan(pfft_plan plan);
 
 /*
- * Per-launch timing.  While enabled, every kernel launch of later calls on
- * this plan is bracketed by two HIP events recorded on the call's stream (no
- * host synchronisation).  pfft_profile_read waits for the logged launches,
+ * Per-launch timing.  While enabled, every stage kernel of later calls on
+ * this plan is launched with hipExtLaunchKernelGGL, which stamps the kernel's
+ * start and end into two HIP events of the plan (no event packets between
+ * kernels, no host synchronisation).  pfft_profile_read waits for the logged launches,
  * fills up to max_entries records (oldest first), sets *n to the number
  * logged, and clears the log.  kind: 0 complex transform, 1 redistribution
  * copy, 2 real-to-complex, 3 complex-to-real, 4 real-to-real; direction: 0 forward, 1 backward,
