@@ -185,7 +185,7 @@ def bench_batch(steps, warmup):
     dev = torch.device("cuda:0")
     uniq = [Plan(s, g, device=dev).bind() for s, g in BATCH_SHAPES]
     tuned = [tune.tuned_plan(s, g, tune_missing=False, device=dev).bind() for s, g in BATCH_SHAPES]
-    n_tuned = sum(1 for p in tuned if getattr(p, "tuned", False))
+    n_tuned = sum(1 for p in tuned if p.tuned)
     members = [p for p in uniq for _ in range(24)]
     tuned_members = [p for p in tuned for _ in range(24)]
     batch = Batch(members, device=dev)
@@ -398,7 +398,7 @@ def plain_record(name, steps, warmup):
            "pct_hbm_peak": round(100.0 * r["step_bytes"] / (r["ms"] * 1e-3) / HBM_PEAK, 2),
            "per_kernel_avg_ms": {k: round(v["ms"] / v["n"], 4) for k, v in r["per_kernel"].items()},
            "roofline": r["roofline"], "roundtrip_rel_l2": r["roundtrip"],
-           "placement": list(r["plan"].placement), "autotuned": bool(getattr(r["plan"], "tuned", False))}
+           "placement": list(r["plan"].placement), "autotuned": r["plan"].tuned}
     del r
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -499,7 +499,7 @@ def main():
                                   "x".join(map(str, grid)), args.path),
                    "shape": list(shape), "grid": list(grid), "kind": kind, "path": args.path,
                    "placement": list(plan.placement), "tuning": plan.tuning(),
-                   "autotuned": bool(getattr(plan, "tuned", False))},
+                   "autotuned": plan.tuned},
         "step_bytes": step_bytes,
         "pct_hbm_peak": round(100.0 * step_bytes / (ms_per_step * 1e-3) / HBM_PEAK, 2) if step_bytes else None,
         "roundtrip_rel_l2": r["roundtrip"],

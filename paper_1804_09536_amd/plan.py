@@ -121,6 +121,7 @@ class Plan:
         check(lib.pfft_num_layouts(h, ctypes.byref(n)), "pfft_num_layouts")
         self.num_layouts = n.value
         self._state = None
+        self.tuned = False  # knobs set from the autotuner's table (tune.tuned_plan)
         self._work = None
 
     def __del__(self):
