@@ -184,11 +184,14 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * times as many with 1024-thread workgroups exchanged in two portions
  * (widest rows, one workgroup per CU), 5 chosen by stage (1 for contiguous
  * and real-to-real stages; 3 for strided lines below 1024 points, 4 at 1024,
- * 6 at 1536, 7 from 2048 on: the measured best, and the default of
- * tile_strided); tile_strided
- * 6 / 7: for complex lines of 1024 points and more, 512 / 1024 threads with
- * one line pair (complex64) or line (complex128) per thread and slot, the
- * LDS exchanging slot groups in turn; lengths without a shape use the
+ * 6 at 1536, 7 from 2048 on; 6 for float real-to-real strided stages: the
+ * measured best, and the default of tile_strided); tile_strided 6 / 7: for
+ * complex lines of 1024 points and more, 512 / 1024 threads with one line
+ * pair (complex64) or line (complex128) per thread and slot, the LDS
+ * exchanging slot groups in turn; for strided real-to-real stages of even
+ * length, the row-addressed kernel (the reordering folded into the row
+ * addresses; 8 / 4 groups of lines per tile, a 16-byte piece of each row per
+ * group); lengths without a shape use the
  * default; resident_*: 1 launches only as many
  * workgroups as the device holds at once, each looping over tiles, 0 one
  * workgroup per tile.  *_contig applies to partial transforms along the last

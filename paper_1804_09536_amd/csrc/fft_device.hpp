@@ -460,6 +460,40 @@ struct SideAddr {
             stride[m] = contig ? (Off)(na[m] * E) : (Off)1;
         }
     }
+
+    // The same for explicit positions pos[m] (each in [0, N)).
+    __device__ __forceinline__ void init_pos(const Side &sd, const Tile &t, int s, const int (&pos)[P], bool contig)
+    {
+        const int rank = t.rank[s];
+        const long O = t.O[s], E = t.E[s], I = t.I[s];
+        if (sd.ublock > 0) {
+            const int un = sd.un;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int j = pos[m];
+                const int c = (unsigned)j / (unsigned)un;
+                const int loc = j - c * un;
+                const long base = (long)(rank + c * sd.R) * sd.ublock;
+                off[m] = (Off)(base + (O * un + loc) * E + I);
+                stride[m] = contig ? (Off)(un * E) : (Off)1;
+            }
+            return;
+        }
+        int2 pc[P];
+#pragma unroll
+        for (int m = 0; m < P; m++) pc[m] = sd.pos[pos[m]];
+        long na[P], base[P];
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            na[m] = sd.na[pc[m].x];
+            base[m] = sd.rank_off[rank + pc[m].x * sd.R];
+        }
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            off[m] = (Off)(base[m] + (O * na[m] + pc[m].y) * E + I);
+            stride[m] = contig ? (Off)(na[m] * E) : (Off)1;
+        }
+    }
 };
 
 }  // namespace pfft

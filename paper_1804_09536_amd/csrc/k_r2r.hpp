@@ -27,6 +27,8 @@
 // reordering out), so global accesses stay in natural order.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_device.hpp"
 #include "k_c2c_impl.hpp"
 #include "pfft_kernels.hpp"
@@ -553,6 +555,306 @@ __global__ __launch_bounds__(S::NT) void k_r2r_half(StageArgs a, const Tile *__r
             if (wl[l] < count) out[dst.off[m] + wl[l] * dst.stride[m]] = rl[ridx(wl[l], jt + m * TPL)];
 }
 
+// Strided half-length stage with the reordering folded into the row
+// addresses: each thread owns RV adjacent lines (one 16-byte piece of every
+// row it touches), loads the rows its points need directly, keeps the lines in
+// registers through the M-point transform and stores its output rows
+// directly; the LDS serves only the transform's exchanges and the pairing of
+// bins k and M-k (no staging of the lines).  SL groups of RV lines per tile.
+template <typename T, int M, int SL>
+struct R2RRowsCfg {
+    using T2 = typename V2<T>::type;
+    static constexpr int RV = 16 / (int)sizeof(T);
+    static constexpr int P = fft_points(M);
+    static constexpr int TPL = M / P;
+    static constexpr int NL = RV;
+    static constexpr int W = SL * RV;
+    static constexpr int NT = TPL * SL;
+    using LT = LdsTile<T2, M, W, false>;
+    static constexpr bool exists = P <= 12 && NT >= 64 && NT <= 1024 && LT::SIZE * (int)sizeof(T2) <= 150 * 1024;
+};
+
+// Element e of a 16-byte row piece (four floats or two doubles).
+__device__ __forceinline__ float piece_get(const float4 &q, int e)
+{
+    return e == 0 ? q.x : e == 1 ? q.y : e == 2 ? q.z : q.w;
+}
+__device__ __forceinline__ double piece_get(const double2 &q, int e) { return e == 0 ? q.x : q.y; }
+
+template <typename T, int M, int SL, bool INV>
+__global__ __launch_bounds__((R2RRowsCfg<T, M, SL>::NT)) void k_r2r_rows(StageArgs a, const Tile *__restrict__ tiles)
+{
+    using C = R2RRowsCfg<T, M, SL>;
+    using T2 = typename C::T2;
+    using LT = typename C::LT;
+    using RVec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    constexpr int N = 2 * M, P = C::P, TPL = C::TPL, NL = C::NL, RV = C::RV, W = C::W;
+    constexpr int FLAG = sizeof(T) == 4 ? 2 : 1;  // rows 16-byte aligned on both sides
+    constexpr bool PT = 2 * (M + 1) * (int)sizeof(T2) <= 8192;
+    __shared__ T2 lds[LT::SIZE];
+    __shared__ T2 twl[TwiddleStage<T2, M>::SIZE];
+    __shared__ T2 ptl[PT ? 2 * (M + 1) : 1];
+    if constexpr (PT)
+        for (int i = threadIdx.x; i < 2 * (M + 1); i += blockDim.x) ptl[i] = ((const T2 *)a.twiddle2)[i];
+    const T2 *tw = TwiddleStage<T2, M>::stage(twl, a.twiddle);
+    if constexpr (PT) __syncthreads();
+    const T2 *te = PT ? (const T2 *)ptl : (const T2 *)a.twiddle2;  // e^{-2 pi i k/N}, k <= M
+    const T2 *tq = te + (M + 1);                                     // e^{-i pi k/2N}, k <= M
+
+    const int tid = threadIdx.x;
+    const int slot = tid % SL, jt = tid / SL;
+    int wl[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) wl[l] = slot * RV + l;
+    const Tile &t = tiles[xcd_tile(blockIdx.x, (int)a.ntiles)];
+    const int count = t.count;
+    const bool vec = count == W && (t.flags & FLAG);
+    constexpr bool inverse = INV;  // type III (the launch picks the kernel by SF_R2R_INVERSE)
+    const bool sine = (a.flags & SF_R2R_SINE) != 0;
+    const bool adj = (a.flags & SF_R2R_ADJOINT) != 0;
+    const bool dbl = adj && inverse;
+    const int special = sine ? N - 1 : 0;
+    const T scale = (T)a.scale;
+    const T *__restrict__ in = (const T *)a.src;
+    T *__restrict__ out = (T *)a.dst;
+    // type II order: element v_i of the reordered line is x_{p(i)}
+    auto p_of = [](int i) { return i < M ? 2 * i : 2 * (N - 1 - i) + 1; };
+
+    // 1. the rows the thread's points need, directly
+    int pos[2 * P];
+#pragma unroll
+    for (int m = 0; m < P; m++) {
+        const int k = jt + m * TPL;
+        if constexpr (!inverse) {
+            pos[2 * m] = p_of(2 * k);
+            pos[2 * m + 1] = p_of(2 * k + 1);
+        } else {
+            // X_k and X_{N-k} (X_M for k = 0) in the type III input order
+            const int j1 = k == 0 ? M : N - k;
+            pos[2 * m] = sine ? N - 1 - k : k;
+            pos[2 * m + 1] = sine ? N - 1 - j1 : j1;
+        }
+    }
+    T x[2 * P][RV];
+    {
+        SideAddr<2 * P> src;
+        src.init_pos(a.side[0], t, 0, pos, false);
+        if (vec) {
+#pragma unroll
+            for (int i = 0; i < 2 * P; i++) {
+                const RVec q = *(const RVec *)(in + src.off[i] + slot * RV);
+#pragma unroll
+                for (int e = 0; e < RV; e++) x[i][e] = piece_get(q, e);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2 * P; i++)
+#pragma unroll
+                for (int e = 0; e < RV; e++) x[i][e] = wl[e] < count ? in[src.off[i] + wl[e]] : (T)0;
+        }
+    }
+
+    // 2. the M-point input
+    T2 v[NL][P];
+    if constexpr (!inverse) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                T x0 = x[2 * m][l], x1 = x[2 * m + 1][l];
+                if (sine && (pos[2 * m] & 1)) x0 = -x0;
+                if (sine && (pos[2 * m + 1] & 1)) x1 = -x1;
+                v[l][m].x = x0;
+                v[l][m].y = x1;
+            }
+    } else {
+        // V_k = e^{+i pi k/2N} (X_k - i X_{N-k}) / 2 (the adjoint of type II
+        // doubles X_0); V_{M-k} comes from the thread that owns M-k (V_M,
+        // owned by nobody, from X_M by the thread of k = 0)
+        T2 vm[NL];
+#pragma unroll
+        for (int l = 0; l < NL; l++) vm[l] = T2{(T)0, (T)0};
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                T xk = x[2 * m][l];
+                if (dbl && k == 0) xk *= (T)2;
+                const T xnk = k == 0 ? (T)0 : x[2 * m + 1][l];
+                const T2 qk = tq[k];
+                v[l][m].x = (T)0.5 * fma(qk.x, xk, -(qk.y * xnk));
+                v[l][m].y = (T)-0.5 * fma(qk.x, xnk, qk.y * xk);
+                if (m == 0) {
+                    const T xc = x[1][l];  // X_M where k = 0
+                    const T2 qc = tq[M];
+                    vm[l].x = (T)0.5 * fma(qc.x, xc, -(qc.y * xc));
+                    vm[l].y = (T)-0.5 * fma(qc.x, xc, qc.y * xc);
+                }
+                lds[LT::idx(wl[l], k)] = v[l][m];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const T2 vk = v[l][m];
+                // (a value select: an LDS load for every k, V_M where k = 0)
+                T2 vc = lds[LT::idx(wl[l], k == 0 ? M - 1 : M - k)];
+                if (k == 0) vc = vm[l];
+                // Z'_k = (V_k + conj V_c) + i e^{+2 pi i k/N} (V_k - conj V_c)
+                const T2 sm = {vk.x + vc.x, vk.y - vc.y};
+                const T2 d = {vk.x - vc.x, vk.y + vc.y};
+                const T2 e = te[k];
+                const T2 ed = {fma(e.x, d.x, e.y * d.y), fma(e.x, d.y, -(e.y * d.x))};
+                v[l][m].x = sm.x - ed.y;
+                v[l][m].y = sm.y + ed.x;
+            }
+        __syncthreads();
+    }
+
+    // 3. the M-point transform
+    if constexpr (inverse)
+        fft_passes<T2, M, W, false, 1, NL, 1, 0>(v, wl, jt, lds, tw);
+    else
+        fft_passes<T2, M, W, false, -1, NL, 1, 0>(v, wl, jt, lds, tw);
+    __syncthreads();
+
+    // 4. outputs (type II pairs bins k and M-k through LDS), by row
+    if constexpr (!inverse) {
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) lds[LT::idx(wl[l], jt + m * TPL)] = v[l][m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const int k = jt + m * TPL;
+            int q0 = k, q1 = k == 0 ? M : N - k;
+            if (sine) {
+                q0 = N - 1 - q0;
+                q1 = N - 1 - q1;
+            }
+            pos[2 * m] = q0;
+            pos[2 * m + 1] = q1;
+        }
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const int k = jt + m * TPL;
+                const T2 zk = v[l][m];
+                T2 zc = lds[LT::idx(wl[l], k == 0 ? 0 : M - k)];
+                zc.y = -zc.y;
+                // X_k = (Z_k + conj Z_c)/2 - (i/2) e^{-2 pi i k/N} (Z_k - conj Z_c)
+                const T2 sm = {(T)0.5 * (zk.x + zc.x), (T)0.5 * (zk.y + zc.y)};
+                const T2 df = {(T)0.5 * (zk.x - zc.x), (T)0.5 * (zk.y - zc.y)};
+                const T2 e = te[k];
+                const T2 ed = {fma(e.x, df.x, -(e.y * df.y)), fma(e.x, df.y, e.y * df.x)};
+                const T2 xk = {sm.x + ed.y, sm.y - ed.x};
+                const T2 q = tq[k];
+                const T2 wx = {fma(q.x, xk.x, -(q.y * xk.y)), fma(q.x, xk.y, q.y * xk.x)};
+                // Y_k = 2 Re(w_k X_k); Y_{N-k} = -2 Im(w_k X_k) (k > 0); bin M from Z_0 (k = 0)
+                T y0 = (T)2 * wx.x * scale;
+                T y1 = k == 0 ? (T)2 * tq[M].x * (zk.x - zk.y) * scale : (T)-2 * wx.y * scale;
+                if (adj && pos[2 * m] == special) y0 *= (T)0.5;
+                if (adj && pos[2 * m + 1] == special) y1 *= (T)0.5;
+                x[2 * m][l] = y0;
+                x[2 * m + 1][l] = y1;
+            }
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const int n = jt + m * TPL;
+            pos[2 * m] = p_of(2 * n);
+            pos[2 * m + 1] = p_of(2 * n + 1);
+        }
+#pragma unroll
+        for (int l = 0; l < NL; l++)
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                T y0 = (T)2 * v[l][m].x * scale, y1 = (T)2 * v[l][m].y * scale;
+                if (sine && (pos[2 * m] & 1)) y0 = -y0;
+                if (sine && (pos[2 * m + 1] & 1)) y1 = -y1;
+                x[2 * m][l] = y0;
+                x[2 * m + 1][l] = y1;
+            }
+    }
+    SideAddr<2 * P> dst;
+    dst.init_pos(a.side[1], t, 1, pos, false);
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < 2 * P; i++) {
+            RVec q;
+            if constexpr (RV == 4)
+                q = make_float4(x[i][0], x[i][1], x[i][2], x[i][3]);
+            else
+                q = make_double2(x[i][0], x[i][1]);
+            *(RVec *)(out + dst.off[i] + slot * RV) = q;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2 * P; i++)
+#pragma unroll
+            for (int e = 0; e < RV; e++)
+                if (wl[e] < count) out[dst.off[i] + wl[e]] = x[i][e];
+    }
+}
+
+template <typename T, int M>
+static bool r2r_rows_cfg(int variant, KernelConfig *cfg)
+{
+    if (variant == 11) {
+        if constexpr (R2RRowsCfg<T, M, 8>::exists) {
+            cfg->W = R2RRowsCfg<T, M, 8>::W;
+            cfg->threads = R2RRowsCfg<T, M, 8>::NT;
+            cfg->id = 11;
+            cfg->resident = 0;
+            return true;
+        }
+    }
+    if (variant == 12) {
+        if constexpr (R2RRowsCfg<T, M, 4>::exists) {
+            cfg->W = R2RRowsCfg<T, M, 4>::W;
+            cfg->threads = R2RRowsCfg<T, M, 4>::NT;
+            cfg->id = 12;
+            cfg->resident = 0;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename T, int M, int SL>
+static hipError_t r2r_rows_launch_sl(const StageArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.ntiles), block(R2RRowsCfg<T, M, SL>::NT);
+    if (a.flags & SF_R2R_INVERSE)
+        PFFT_LAUNCH((k_r2r_rows<T, M, SL, true>), grid, block, 0, s, a, a.tiles);
+    else
+        PFFT_LAUNCH((k_r2r_rows<T, M, SL, false>), grid, block, 0, s, a, a.tiles);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+static bool r2r_rows_launch(int variant, const StageArgs &a, hipStream_t s, hipError_t *e)
+{
+    if (variant == 11) {
+        if constexpr (R2RRowsCfg<T, M, 8>::exists) {
+            *e = r2r_rows_launch_sl<T, M, 8>(a, s);
+            return true;
+        }
+    }
+    if (variant == 12) {
+        if constexpr (R2RRowsCfg<T, M, 4>::exists) {
+            *e = r2r_rows_launch_sl<T, M, 4>(a, s);
+            return true;
+        }
+    }
+    return false;
+}
+
 template <typename T, int N, bool CONTIG, int V>
 static void r2r_shape(KernelConfig *cfg)
 {
@@ -607,7 +909,7 @@ static int r2r_config_t(int N, int contig, int variant, KernelConfig *cfg)
     case n:                                                                                   \
         if (contig)                                                                           \
             (v == 1 ? r2r_shape<T, n, true, 1> : r2r_shape<T, n, true, 0>)(cfg);             \
-        else                                                                                  \
+        else if (!r2r_rows_cfg<T, n>(variant, cfg))                                           \
             (v == 1 ? r2r_shape<T, n, false, 1> : r2r_shape<T, n, false, 0>)(cfg);           \
         return 0;
             PFFT_FOR_EACH_N(PFFT_CASE)
@@ -637,6 +939,10 @@ static hipError_t r2r_launch_t(int N, int contig, int variant, const StageArgs &
     case n:                                                                                                   \
         if (contig)                                                                                           \
             return variant == 1 ? r2r_launch_half<T, n, true, 1>(a, s) : r2r_launch_half<T, n, true, 0>(a, s); \
+        {                                                                                                      \
+            hipError_t e_ = hipSuccess;                                                                        \
+            if (r2r_rows_launch<T, n>(variant, a, s, &e_)) return e_;                                          \
+        }                                                                                                      \
         return variant == 1 ? r2r_launch_half<T, n, false, 1>(a, s) : r2r_launch_half<T, n, false, 0>(a, s);
             PFFT_FOR_EACH_N(PFFT_CASE)
 #undef PFFT_CASE

@@ -678,16 +678,23 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     // the long-line shapes from 1536 points: 512 threads at 1536, 1024
     // beyond; real-to-real stages are fastest with more, smaller workgroups,
     // real-to-complex stages with a quarter of the default lines per tile:
-    // 512^3 0.264 -> 0.247 ms, while complex-to-real stages lose 12 % there)
+    // 512^3 0.264 -> 0.247 ms, while complex-to-real stages lose 12 % there;
+    // strided real-to-real stages in complex64 with the row-addressed kernel:
+    // 512^3 type II cosine transform 1.61 -> 1.51 ms, while complex128 loses)
     if (variant == 5)
-        variant = ln.kind == KIND_R2C                        ? 2
-                  : (ln.contig || ln.kind == KIND_R2R) ? 1
+        variant = ln.kind == KIND_R2C                                      ? 2
+                  : (ln.kind == KIND_R2R && !ln.contig && prec == PFFT_F32) ? 6
+                  : (ln.contig || ln.kind == KIND_R2R)               ? 1
                   : ln.N < 1024                      ? 3
                   : ln.N == 1024                     ? 4
                   : ln.N == 1536                     ? 6
                                                      : 7;
-    // 6 / 7: the slot-group shapes of complex strided stages (kernel variants 9 / 10)
-    if (variant == 6 || variant == 7) variant = (ln.kind == KIND_C2C && !ln.contig) ? variant + 3 : 0;
+    // 6 / 7: the slot-group shapes of complex strided stages (kernel variants 9 / 10),
+    // the row-addressed kernel of strided real-to-real stages (11 / 12)
+    if (variant == 6 || variant == 7)
+        variant = (ln.kind == KIND_C2C && !ln.contig)   ? variant + 3
+                  : (ln.kind == KIND_R2R && !ln.contig) ? variant + 5
+                                                        : 0;
     int rc;
     if (ln.mixed_sides && ln.kind != KIND_COPY) {
         // lines contiguous on one side and adjacent on the other: the stage

@@ -63,6 +63,34 @@ def test_r2r_forward_backward_adjoints_match_oracle(shape, grid, kinds, prec, no
     assert relerr(gb.astype(np.float64), oracle.adjoint_backward(ch, u.astype(np.float64))) <= TOL[prec]
 
 
+# The row-addressed kernel of strided stages (tile_strided 6 and 7): every
+# kind, both directions and both adjoints, full and partial tiles, both
+# precisions.
+@pytest.mark.parametrize("ts", [6, 7])
+@pytest.mark.parametrize("shape,grid,kinds,prec", [
+    ((64, 32, 16), (4, 4), ("dct2", "dst2", "dct2"), "f32"),
+    ((96, 48, 24), (2, 3), ("dst2", "dct2", "dst2"), "f32"),
+    ((128, 12, 24), (2, 2), ("dct2", "dct2", "dst2"), "f64"),
+    ((512, 8, 32), (2, 2), ("dst2", "dst2", "dct2"), "f32"),
+])
+def test_r2r_row_kernel_matches_oracle(shape, grid, kinds, prec, ts):
+    print("case", shape, grid, kinds, prec, ts, flush=True)
+    p = Plan(shape, grid, kind="r2r", r2r=kinds, precision=prec)
+    p.set_tuning(tile_strided=ts)
+    p.validate()
+    ch = oracle.Chain.paper(shape, grid, kind="r2r", r2r=kinds)
+    u = inputs.gaussian_real(p.buffer_numel(0), [24, ts], RDT[prec])
+    got = _host(p.forward(_to_dev(u)))
+    assert relerr(got.astype(np.float64), oracle.forward(ch, u.astype(np.float64))) <= TOL[prec]
+    back = _host(p.backward(_to_dev(got)))
+    assert relerr(back.astype(np.float64), oracle.backward(ch, got.astype(np.float64))) <= TOL[prec]
+    z = inputs.gaussian_real(p.buffer_numel(p.num_layouts - 1), [25, ts], RDT[prec])
+    ga = _host(p.adjoint_forward(_to_dev(z)))
+    assert relerr(ga.astype(np.float64), oracle.adjoint_forward(ch, z.astype(np.float64))) <= TOL[prec]
+    gb = _host(p.adjoint_backward(_to_dev(u)))
+    assert relerr(gb.astype(np.float64), oracle.adjoint_backward(ch, u.astype(np.float64))) <= TOL[prec]
+
+
 @pytest.mark.parametrize("path", ["unfused", "pack_realign"])
 def test_r2r_other_paths_equal_fused(path):
     shape, grid, kinds = (24, 16, 32), (2, 4), ("dst2", "dct2", "dst2")
