@@ -55,10 +55,16 @@ struct RealStage {
         }
     }
 
-    // One tile of the stage (arguments a, tile t).
-    __device__ static __forceinline__ void run(const StageArgs &a, const Tile &t, T2 *lds, const T2 *__restrict__ tw,
-                                               const T2 *__restrict__ tw2)
+    // One tile of the stage (arguments a, tile t), with the twiddle tables of
+    // ta staged in twl: while the tile's loads are in flight in complex-to-real
+    // stages and in single-precision real-to-complex stages, before them in
+    // double-precision real-to-complex stages (measured faster each way).
+    static constexpr bool LATE_TW = KIND == KIND_C2R || sizeof(T) == 4;
+    __device__ static __forceinline__ void run(const StageArgs &a, const Tile &t, T2 *lds, T2 *twl,
+                                               const StageArgs &ta)
     {
+        const T2 *tw = nullptr, *tw2 = nullptr;
+        if constexpr (!LATE_TW) stage_twiddles(ta, twl, tw, tw2);
         const int count = t.count;
         const int tid = threadIdx.x;
         const int jt = tid % TPL;
@@ -92,6 +98,7 @@ struct RealStage {
                     for (int m = 0; m < P; m++)
                         v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
             }
+            if constexpr (LATE_TW) stage_twiddles(ta, twl, tw, tw2);
             fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
             __syncthreads();
 #pragma unroll
@@ -175,6 +182,7 @@ struct RealStage {
                     xm[l] = valid[l] ? in[addr] : c_zero<T2>();
                 }
             }
+            if constexpr (LATE_TW) stage_twiddles(ta, twl, tw, tw2);
 #pragma unroll
             for (int l = 0; l < NL; l++) {
 #pragma unroll
@@ -240,9 +248,7 @@ __global__ __launch_bounds__(S::NT) void k_real(StageArgs a, const Tile *__restr
     using T2 = typename R::T2;
     __shared__ T2 lds[R::LDS_N];
     __shared__ T2 twl[R::TW_N];
-    const T2 *tw, *tw2;
-    R::stage_twiddles(a, twl, tw, tw2);
-    R::run(a, tiles[blockIdx.x], lds, tw, tw2);
+    R::run(a, tiles[blockIdx.x], lds, twl, a);
 }
 
 // The same stage over the tiles of several transforms in one launch (a
@@ -257,10 +263,8 @@ __global__ __launch_bounds__(S::NT) void k_real_multi(const StageArgs *__restric
     using T2 = typename R::T2;
     __shared__ T2 lds[R::LDS_N];
     __shared__ T2 twl[R::TW_N];
-    const T2 *tw, *tw2;
-    R::stage_twiddles(args[0], twl, tw, tw2);
     const Tile &t = tiles[blockIdx.x];
-    R::run(args[t.flags >> 8], t, lds, tw, tw2);
+    R::run(args[t.flags >> 8], t, lds, twl, args[0]);
 }
 
 #define PFFT_FOR_EACH_NR(X)                                                                             \
@@ -269,7 +273,8 @@ __global__ __launch_bounds__(S::NT) void k_real_multi(const StageArgs *__restric
 
 // Launch shapes: variant 1 (half the lines per tile) where it exists, else
 // the default; variant 2 a quarter of the default lines, one line per slot
-// (more, smaller workgroups per CU).
+// (more, smaller workgroups per CU).  (Two lines per slot in quarter-width
+// tiles measured no faster than the better of these for either kind.)
 template <typename T, int NR>
 struct RealQuarter {
     using D = C2CDefault<T, NR / 2, true>;

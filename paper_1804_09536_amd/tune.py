@@ -41,9 +41,18 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "paper_1804_09536_amd", "tune.json"))
 
 
+def device_id(dev: int = 0) -> str:
+    """The device's instruction set and compute-unit count, e.g.
+    "gfx950/256cu" (the marketing name depends on the driver's name tables,
+    which differ between processes, e.g. under a profiler)."""
+    p = torch.cuda.get_device_properties(dev)
+    arch = (getattr(p, "gcnArchName", "") or p.name).split(":")[0]
+    return "%s/%dcu" % (arch, p.multi_processor_count)
+
+
 def _key(shape, grid, kind, precision, chain, path) -> str:
     return json.dumps({"shape": list(shape), "grid": list(grid), "kind": kind, "precision": precision,
-                       "chain": chain, "path": path, "device": torch.cuda.get_device_name(0)}, sort_keys=True)
+                       "chain": chain, "path": path, "device": device_id(0)}, sort_keys=True)
 
 
 def _load_cache(path):

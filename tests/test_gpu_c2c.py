@@ -239,6 +239,37 @@ def test_tuning_knobs_do_not_change_results(shape, grid, kind):
             assert _host(p.backward(_to_dev(ref))).tobytes() == ref_b.tobytes(), (placement, sc)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape,grid", [((6, 10, 512), (2, 3)), ((5, 6, 1024), (2, 2)), ((4, 6, 384), (2, 3))])
+def test_real_stage_shapes(shape, grid, prec):
+    # every launch shape of the real-to-complex and complex-to-real stages
+    # (tile_contig 0-3: the default, half and quarter-width tiles; 3 takes the
+    # default) on ragged blocks (partial tiles), with the twiddle tables staged
+    # before or during the loads by precision: bitwise equal results, the
+    # oracle's within tolerance
+    print("case", shape, grid, prec, flush=True)
+    rdt, tol = (np.float32, 1e-5) if prec == "f32" else (np.float64, 1e-12)
+    u = inputs.gaussian_real(Plan(shape, grid, kind="r2c", precision=prec).buffer_numel(0, real=True), [6], rdt)
+    x = _to_dev(u)
+    ref = ref_b = None
+    for tc in range(4):
+        p = Plan(shape, grid, kind="r2c", precision=prec)
+        p.set_tuning(tile_contig=tc)
+        p.validate()
+        got = _host(p.forward(x))
+        back = _host(p.backward(_to_dev(got)))
+        if ref is None:
+            ch = oracle.Chain.paper(shape, grid, kind="r2c")
+            expect = oracle.forward(ch, u.astype(np.float64))
+            assert np.linalg.norm(got - expect) / np.linalg.norm(expect) <= tol
+            expect_b = oracle.backward(ch, got.astype(np.complex128))
+            assert np.linalg.norm(back - expect_b) / np.linalg.norm(expect_b) <= tol
+            ref, ref_b = got, back
+        else:
+            assert got.tobytes() == ref.tobytes(), tc
+            assert back.tobytes() == ref_b.tobytes(), tc
+
+
 @pytest.mark.parametrize("shape,grid,kind,placement,path", [
     ((64, 32, 16), (4, 4), "c2c", None, "fused"),
     ((8, 12, 8, 16), (2, 3, 2), "c2c", None, "fused"),
