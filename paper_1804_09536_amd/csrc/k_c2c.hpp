@@ -396,10 +396,11 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];
     __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
-    // the twiddle table is staged while the first tile's loads are in flight,
-    // except in single-precision contiguous stages, which stage it first
-    // (measured faster each way)
-    constexpr bool late_tw = !CONTIG || sizeof(T) == 8;
+    // SF_LATE_TWIDDLES: the twiddle table is staged while the first tile's
+    // loads are in flight (single-precision contiguous stages measured faster
+    // staging it first in every case)
+    constexpr bool late_ok = !CONTIG || sizeof(T) == 8;
+    const bool late_tw = late_ok && (a.flags & SF_LATE_TWIDDLES);
     const T2 *tw = late_tw ? nullptr : TwiddleStage<T2, N>::stage(twl, a.twiddle);
     Wk wk;
     wk.init_geometry();
@@ -422,8 +423,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
         // vector path)
         const Tile &t = CONTIG ? a.tiles[ti] : tiles[ti];
         wk.load(a, t, v, d, c);
-        if constexpr (late_tw)
-            if (ti0 == blockIdx.x) tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);
+        if (late_tw && ti0 == blockIdx.x) tw = TwiddleStage<T2, N>::stage(twl, a.twiddle);
         wk.process(a, t, v, d, c, lds, tw);
     }
 }
@@ -442,8 +442,7 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
     constexpr int NL = S::NL, P = S::P;
     __shared__ T2 lds[Wk::LDS_SIZE];
     __shared__ T2 twl[TwiddleStage<T2, N>::SIZE];
-    constexpr bool late_tw = !CONTIG || sizeof(T) == 8;
-    const T2 *tw = late_tw ? nullptr : TwiddleStage<T2, N>::stage(twl, args[0].twiddle);
+    const T2 *tw = TwiddleStage<T2, N>::stage(twl, args[0].twiddle);
     Wk wk;
     wk.init_geometry();
     const long G = gridDim.x;
@@ -455,8 +454,6 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(c2c_waves
         const StageArgs &a = args[(unsigned)t.flags >> 8];
         wk.refresh();
         wk.load(a, t, v, d, c);
-        if constexpr (late_tw)
-            if (ti == blockIdx.x) tw = TwiddleStage<T2, N>::stage(twl, args[0].twiddle);
         wk.process(a, t, v, d, c, lds, tw);
     }
 }

@@ -56,15 +56,17 @@ struct RealStage {
     }
 
     // One tile of the stage (arguments a, tile t), with the twiddle tables of
-    // ta staged in twl: while the tile's loads are in flight in complex-to-real
-    // stages and in single-precision real-to-complex stages, before them in
-    // double-precision real-to-complex stages (measured faster each way).
-    static constexpr bool LATE_TW = KIND == KIND_C2R || sizeof(T) == 4;
+    // ta staged in twl: with SF_LATE_TWIDDLES while the tile's loads are in
+    // flight in complex-to-real stages and in single-precision real-to-complex
+    // stages, else before them (double-precision real-to-complex stages
+    // measured faster that way).
+    static constexpr bool LATE_OK = KIND == KIND_C2R || sizeof(T) == 4;
     __device__ static __forceinline__ void run(const StageArgs &a, const Tile &t, T2 *lds, T2 *twl,
                                                const StageArgs &ta)
     {
         const T2 *tw = nullptr, *tw2 = nullptr;
-        if constexpr (!LATE_TW) stage_twiddles(ta, twl, tw, tw2);
+        const bool late_tw = LATE_OK && (ta.flags & SF_LATE_TWIDDLES);
+        if (!late_tw) stage_twiddles(ta, twl, tw, tw2);
         const int count = t.count;
         const int tid = threadIdx.x;
         const int jt = tid % TPL;
@@ -98,7 +100,7 @@ struct RealStage {
                     for (int m = 0; m < P; m++)
                         v[l][m] = valid[l] ? *(const T2 *)(in + rs.off[m] + wl[l] * rs.stride[m]) : c_zero<T2>();
             }
-            if constexpr (LATE_TW) stage_twiddles(ta, twl, tw, tw2);
+            if (late_tw) stage_twiddles(ta, twl, tw, tw2);
             fft_passes<T2, M, W, true, -1, NL, 1, 0>(v, wl, jt, lds, tw);
             __syncthreads();
 #pragma unroll
@@ -182,7 +184,7 @@ struct RealStage {
                     xm[l] = valid[l] ? in[addr] : c_zero<T2>();
                 }
             }
-            if constexpr (LATE_TW) stage_twiddles(ta, twl, tw, tw2);
+            if (late_tw) stage_twiddles(ta, twl, tw, tw2);
 #pragma unroll
             for (int l = 0; l < NL; l++) {
 #pragma unroll

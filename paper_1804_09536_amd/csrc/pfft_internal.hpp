@@ -72,6 +72,9 @@ enum StageFlags : int32_t {
                              // (workgroup b runs on XCD b % 8) takes one contiguous range of tiles
     SF_LOAD_NT = 64,         // complex strided stage: full aligned tiles read with streaming loads
     SF_STORE_NT = 128,       // complex strided stage: full aligned tiles written with streaming stores
+    SF_LATE_TWIDDLES = 256,  // the workgroup stages its twiddle table in LDS while its first loads are
+                             // in flight (complex strided and FP64 stages, real stages of the kinds
+                             // that gain; set on stages beyond the last-level cache)
 };
 
 struct StageArgs {
