@@ -779,11 +779,14 @@ static int finish_launch(pfft_plan_s *p, Launch &ln)
     // those loads come from HBM (source and destination beyond the last-level
     // cache: 512^3 strided stages -1..-3 %, real stages -3..-6 %); stages on
     // cached buffers measured 0.5-2 % slower that way (the 168-transform
-    // batch), so they stage the table first.
+    // batch), so they stage the table first.  PFFT_LATE_TWIDDLES=1 in the
+    // environment at plan creation takes the late order on every stage (for
+    // tests: both orders give bitwise equal results).
     {
         const double esz = p->precision == PFFT_F32 ? 8.0 : 16.0;
         const double bytes = ((double)p->layouts[ln.src].total() + (double)p->layouts[ln.dst].total()) * esz;
-        ln.late_tw = bytes > 256.0 * 1048576.0 ? 1 : 0;
+        const char *force = getenv("PFFT_LATE_TWIDDLES");
+        ln.late_tw = (bytes > 256.0 * 1048576.0 || (force && strcmp(force, "1") == 0)) ? 1 : 0;
     }
     return PFFT_OK;
 }
