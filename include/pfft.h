@@ -202,6 +202,10 @@ int pfft_plan_create_r2r(pfft_plan *out, int ndim, const int64_t *global_shape, 
  * continue over consecutive short runs of lines (inner extents below the
  * tile width) where the blocks allow it.  xcd_order: see the field.  pfft_plan_set_tuning rebuilds the plan's
  * tables: query pfft_device_state_bytes again and bind again before use.
+ * Not a field: stages on buffers beyond the 256 MiB last-level cache stage
+ * their twiddle tables while their first loads are in flight, others first;
+ * PFFT_LATE_TWIDDLES=1 in the environment at plan creation (or set_tuning)
+ * takes the late order on every stage.  Results are bitwise the same.
  */
 typedef struct {
     int tile_contig;
