@@ -43,8 +43,8 @@ def cache_path() -> str:
 
 def device_id(dev: int = 0) -> str:
     """The device's instruction set and compute-unit count, e.g.
-    "gfx950/256cu" (the marketing name depends on the driver's name tables,
-    which differ between processes, e.g. under a profiler)."""
+    "gfx950/256cu" (the marketing name comes from name tables that are not
+    found in every process, e.g. under a profiler)."""
     p = torch.cuda.get_device_properties(dev)
     arch = (getattr(p, "gcnArchName", "") or p.name).split(":")[0]
     return "%s/%dcu" % (arch, p.multi_processor_count)
